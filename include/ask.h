@@ -1,0 +1,167 @@
+/*
+ * ask.h -- C ABI of the MI355X (gfx950) library for Mandelbrot dwell images
+ * by exhaustive evaluation and by Mariani-Silver subdivision, run as
+ * Adaptive Serial Kernels (per-level kernels over a compact region queue) or
+ * as one persistent kernel over a device-resident region queue.
+ *
+ * Paper: Quezada, Navarro, Romero, Aguilera, "Modeling GPU Dynamic
+ * Parallelism for Self Similar Density Workloads" (arXiv 2206.02255).
+ *   - dwell of c: Sec. 6 (z_{i+1} = z_i^2 + c, z_0 = 0, escape radius 2);
+ *   - exhaustive image: Sec. 4.1 (W_E = n^2 A, one work unit per pixel);
+ *   - subdivision: Sec. 4.2 and 4.2.1 (initial g x g grid, border query Q,
+ *     uniform border -> fill T, otherwise split r x r at cost S, until regions
+ *     reach the stop size B, then per-pixel work L);
+ *   - level-by-level execution with an offset lookup table that is appended
+ *     with one atomic add per splitting region and swapped between levels:
+ *     Sec. 5.1-5.3.
+ *
+ * Conventions shared by every call
+ *   - Plain C types only; no exception crosses the ABI. Every call returns an
+ *     ask_status; ASK_OK is 0, errors are negative.
+ *   - Images are W x H uint32 dwell values in device memory, row-major
+ *     (index py*W + px), row 0 on the y0 side. The caller owns them; the
+ *     library never allocates or frees them.
+ *   - Pixel (px, py) maps to c = (cxm + (2px+1-W) hx, cym + (2py+1-H) hy)
+ *     with cxm = (x0+x1)/2, cym = (y0+y1)/2, hx = (x1-x0)/(2W),
+ *     hy = (y1-y0)/(2H), each operation rounded to binary64 on its own; the
+ *     dwell loop is evaluated in binary64 without fused multiply-add, so the
+ *     images are bit-for-bit reproducible.
+ *   - Calls enqueue work on the given HIP stream (hipStream_t passed as
+ *     void*, NULL = the default stream) and return without waiting, except
+ *     where stated. Argument errors are reported synchronously.
+ *   - A context is bound to one device and is not thread-safe; use one per
+ *     host thread. Calls on one context must be ordered on one stream, as
+ *     they share the context's queue memory.
+ */
+#ifndef ASK_H
+#define ASK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ASK_MAX_LEVELS 64
+
+typedef enum ask_status {
+    ASK_OK = 0,
+    ASK_EINVAL = -1,    /* bad argument (window, params, pointer) */
+    ASK_ENOMEM = -2,    /* device or host allocation failed */
+    ASK_EDEVICE = -3,   /* HIP runtime error; see ask_last_error */
+    ASK_EOVERFLOW = -4, /* the region queue was too small; the image is invalid */
+    ASK_EBUSY = -5,     /* cannot accept the request now */
+    ASK_ETIMEOUT = -6   /* a wait ran out of time */
+} ask_status;
+
+/* A complex window [x0, x1] x [y0, y1] rendered at W x H pixels with
+ * maximum dwell D. Valid: finite bounds, x0 < x1, y0 < y1,
+ * 1 <= W, H <= 65536, 1 <= D <= 2^31 - 1. */
+typedef struct ask_window {
+    double x0, x1, y0, y1;
+    uint32_t W, H, D;
+    uint32_t reserved; /* must be 0 */
+} ask_window;
+
+/* Execution form of a subdivision render. */
+typedef enum ask_form {
+    /* Adaptive Serial Kernels (Sec. 5): one kernel per level; every kernel
+     * reads the level's region count from device memory, so the host never
+     * waits between levels. */
+    ASK_FORM_LEVELS = 0,
+    /* The same, with the region count read back to the host after every
+     * level to size the next grid, as the paper's host loop does (Sec.
+     * 5.3.2). Synchronises the stream once per level. */
+    ASK_FORM_LEVELS_READBACK = 1,
+    /* One persistent kernel whose waves pull regions from a device-resident
+     * queue until all work is done. */
+    ASK_FORM_PERSISTENT = 2
+} ask_form;
+
+/* Subdivision parameters (Sec. 4.2.1, 6.2): an initial g x g grid of
+ * regions, r x r splits, stop size B (a region with both sides <= B whose
+ * border is not uniform is computed per pixel). Valid: 1 <= g <= min(W, H),
+ * 2 <= r <= 8, 1 <= B <= 65536. form: an ask_form. */
+typedef struct ask_params {
+    uint32_t g, r, B;
+    uint32_t form;
+} ask_params;
+
+/* Work counters of a render, filled when the caller asks for them. */
+typedef struct ask_stats {
+    uint32_t levels;                       /* deepest level reached + 1 */
+    uint32_t overflow;                     /* nonzero: queue capacity exceeded */
+    uint64_t regions[ASK_MAX_LEVELS];      /* regions scanned per level */
+    uint64_t fills[ASK_MAX_LEVELS];        /* uniform border -> filled */
+    uint64_t splits[ASK_MAX_LEVELS];       /* split into children */
+    uint64_t leaves[ASK_MAX_LEVELS];       /* computed per pixel */
+    uint64_t iters_ring;                   /* sum of dwells computed on borders */
+    uint64_t iters_leaf;                   /* sum of dwells computed in leaves */
+} ask_stats;
+
+typedef struct ask_ctx ask_ctx;
+
+/* Human-readable name of a status code (static storage). */
+const char *ask_status_str(ask_status s);
+
+/* Text of the last error on this context (static per context; never NULL). */
+const char *ask_last_error(const ask_ctx *ctx);
+
+/* Create a context on HIP device `device`. *out receives the context, or
+ * NULL on error. Returns ASK_EDEVICE when no such device exists. */
+ask_status ask_create(ask_ctx **out, int device);
+
+/* Release a context and all device memory it owns (after waiting for its
+ * work). NULL is accepted. */
+ask_status ask_destroy(ask_ctx *ctx);
+
+/* Host-only helpers (no device needed). */
+
+/* Check a window (and params, when not NULL) for validity. */
+ask_status ask_validate(const ask_window *win, const ask_params *params);
+
+/* Mapping constants {cxm, cym, hx, hy} of a window, as the kernels use them. */
+ask_status ask_mapping(const ask_window *win, double out[4]);
+
+/* Number of levels a subdivision can reach: 1 + the number of r-fold
+ * splits that take the largest level-0 side down to B or below. */
+ask_status ask_level_count(const ask_window *win, const ask_params *params,
+                           uint32_t *levels);
+
+/* Exhaustive image (Sec. 4.1): d_out[py*W + px] = dwell(c(px, py)) for all
+ * pixels. d_out: device memory, W*H uint32, caller-owned. */
+ask_status ask_dwell_exhaustive(ask_ctx *ctx, const ask_window *win,
+                                uint32_t *d_out, void *stream);
+
+/* Subdivision image (Sec. 4.2.1, 5): every region of the initial g x g grid
+ * has its border dwells computed; a uniform border fills the region with
+ * that value, otherwise the region is computed per pixel when both its
+ * sides are <= B, or split into its r x r floor partition (pieces
+ * [a + j*len/r, a + (j+1)*len/r), empty pieces dropped). d_out as above.
+ * stats: NULL, or receives the work counters; a non-NULL stats makes the
+ * call wait for the stream and return any error the render recorded (as
+ * ask_synchronize does). The call also waits for the stream when the queue
+ * could overflow (very large images with tiny B); an overflow then returns
+ * ASK_EOVERFLOW. Otherwise device-side errors surface at ask_synchronize. */
+ask_status ask_dwell_subdiv(ask_ctx *ctx, const ask_window *win,
+                            const ask_params *params, uint32_t *d_out,
+                            void *stream, ask_stats *stats);
+
+/* Wait for `stream`, then report the errors the kernels recorded on this
+ * context since the last check: ASK_ETIMEOUT when a persistent wave gave up
+ * waiting (see ask_set_wait_limit), else ASK_EOVERFLOW when a queue ran out
+ * of room, else ASK_OK. The recorded errors are cleared. A render that
+ * reports either error has left an invalid image. */
+ask_status ask_synchronize(ask_ctx *ctx, void *stream);
+
+/* Longest time, in seconds (0 to 3600, default 10), that one wave of the
+ * persistent kernel waits for a region before it records ASK_ETIMEOUT and
+ * leaves. This bounds every wait of the kernel, so its grid always drains;
+ * a render never legitimately idles a wave for seconds. */
+ask_status ask_set_wait_limit(ask_ctx *ctx, double seconds);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,156 @@
+"""Python binding of ``libask.so`` (include/ask.h): argument marshalling only.
+
+Every call goes straight to the C ABI; all of the work runs in the gfx950
+kernels. Device memory and streams come from PyTorch: pass a tensor's
+``data_ptr()`` and ``torch.cuda.current_stream().cuda_stream``. There is no
+fallback: if the library is not built, importing this module raises.
+"""
+import ctypes as C
+import os
+
+# PyTorch ships its own HIP runtime with the same soname as the system one.
+# Loading it first makes libask.so bind to that same runtime, so that the
+# streams and device pointers PyTorch hands over are valid in the library.
+import torch  # noqa: F401
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libask.so")
+
+MAX_LEVELS = 64
+OK, EINVAL, ENOMEM, EDEVICE, EOVERFLOW, EBUSY, ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
+FORM_LEVELS, FORM_LEVELS_READBACK, FORM_PERSISTENT = 0, 1, 2
+FORMS = {"levels": FORM_LEVELS, "levels_readback": FORM_LEVELS_READBACK,
+         "persistent": FORM_PERSISTENT}
+
+
+class AskError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (status %d)" % (msg, status))
+        self.status = status
+
+
+class ask_window(C.Structure):
+    _fields_ = [("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
+                ("W", C.c_uint32), ("H", C.c_uint32), ("D", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class ask_params(C.Structure):
+    _fields_ = [("g", C.c_uint32), ("r", C.c_uint32), ("B", C.c_uint32), ("form", C.c_uint32)]
+
+
+class ask_stats(C.Structure):
+    _fields_ = [("levels", C.c_uint32), ("overflow", C.c_uint32),
+                ("regions", C.c_uint64 * MAX_LEVELS), ("fills", C.c_uint64 * MAX_LEVELS),
+                ("splits", C.c_uint64 * MAX_LEVELS), ("leaves", C.c_uint64 * MAX_LEVELS),
+                ("iters_ring", C.c_uint64), ("iters_leaf", C.c_uint64)]
+
+    def as_dict(self):
+        n = self.levels
+        d = {"levels": n, "overflow": self.overflow, "iters_ring": self.iters_ring,
+             "iters_leaf": self.iters_leaf}
+        for k in ("regions", "fills", "splits", "leaves"):
+            d[k] = list(getattr(self, k)[:n])
+        return d
+
+
+# Every symbol include/ask.h declares, with its C signature.
+_P = C.c_void_p
+SIGNATURES = {
+    "ask_status_str": (C.c_char_p, [C.c_int]),
+    "ask_last_error": (C.c_char_p, [_P]),
+    "ask_create": (C.c_int, [C.POINTER(_P), C.c_int]),
+    "ask_destroy": (C.c_int, [_P]),
+    "ask_validate": (C.c_int, [C.POINTER(ask_window), C.POINTER(ask_params)]),
+    "ask_mapping": (C.c_int, [C.POINTER(ask_window), C.POINTER(C.c_double)]),
+    "ask_level_count": (C.c_int, [C.POINTER(ask_window), C.POINTER(ask_params),
+                                  C.POINTER(C.c_uint32)]),
+    "ask_dwell_exhaustive": (C.c_int, [_P, C.POINTER(ask_window), _P, _P]),
+    "ask_dwell_subdiv": (C.c_int, [_P, C.POINTER(ask_window), C.POINTER(ask_params), _P, _P,
+                                   C.POINTER(ask_stats)]),
+    "ask_synchronize": (C.c_int, [_P, _P]),
+    "ask_set_wait_limit": (C.c_int, [_P, C.c_double]),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libask.so is not built (expected at %s); build it with "
+                          "paper_2206_02255_amd.build.build()" % LIB_PATH)
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def status_str(s):
+    return lib.ask_status_str(s).decode()
+
+
+def window(w):
+    """ask_window from any object with x0, x1, y0, y1, W, H, D."""
+    return ask_window(float(w.x0), float(w.x1), float(w.y0), float(w.y1),
+                      int(w.W), int(w.H), int(w.D), 0)
+
+
+def params(g, r, B, form="levels"):
+    return ask_params(int(g), int(r), int(B), FORMS[form] if isinstance(form, str) else int(form))
+
+
+def _check(s, ctx=None):
+    if s != OK:
+        msg = status_str(s)
+        if ctx:
+            detail = lib.ask_last_error(ctx)
+            if detail:
+                msg += ": " + detail.decode()
+        raise AskError(s, msg)
+
+
+def ask_validate(win, prm=None):
+    return lib.ask_validate(C.byref(win), C.byref(prm) if prm is not None else None)
+
+
+def ask_mapping(win):
+    m = (C.c_double * 4)()
+    _check(lib.ask_mapping(C.byref(win), m))
+    return tuple(m)
+
+
+def ask_level_count(win, prm):
+    n = C.c_uint32()
+    _check(lib.ask_level_count(C.byref(win), C.byref(prm), C.byref(n)))
+    return n.value
+
+
+def ask_create(device=0):
+    h = _P()
+    _check(lib.ask_create(C.byref(h), int(device)))
+    return h
+
+
+def ask_destroy(ctx):
+    _check(lib.ask_destroy(ctx))
+
+
+def ask_dwell_exhaustive(ctx, win, d_out, stream=0):
+    _check(lib.ask_dwell_exhaustive(ctx, C.byref(win), _P(d_out), _P(stream)), ctx)
+
+
+def ask_dwell_subdiv(ctx, win, prm, d_out, stream=0, want_stats=False):
+    st = ask_stats() if want_stats else None
+    _check(lib.ask_dwell_subdiv(ctx, C.byref(win), C.byref(prm), _P(d_out), _P(stream),
+                                C.byref(st) if st is not None else None), ctx)
+    return st.as_dict() if st is not None else None
+
+
+def ask_synchronize(ctx, stream=0):
+    _check(lib.ask_synchronize(ctx, _P(stream)), ctx)
+
+
+def ask_set_wait_limit(ctx, seconds):
+    _check(lib.ask_set_wait_limit(ctx, float(seconds)), ctx)

@@ -1,0 +1,544 @@
+// gfx950 kernels: the dwell core, the exhaustive image, and the subdivision
+// (Mariani-Silver) kernels in their per-level and persistent forms.
+//
+// Every floating-point operation of the dwell is a separate binary64 add or
+// multiply: the file is compiled with -ffp-contract=off and also forbids
+// contraction below, so no v_fma_f64 can appear and the images equal those of
+// the binary64 definition bit for bit.
+#pragma clang fp contract(off)
+
+#include "ask_internal.hpp"
+
+namespace ask {
+
+// ---------------------------------------------------------------------------
+// Pixel -> c (the host computed cxm, cym, hx, hy; the device never divides).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void pixel_c(const Image &im, uint32_t px, uint32_t py,
+                                        double &cr, double &ci) {
+    const int kx = 2 * (int)px + 1 - (int)im.W;   // odd, |kx| < 2^17: exact
+    const int ky = 2 * (int)py + 1 - (int)im.H;
+    const double tx = (double)kx * im.hx;
+    const double ty = (double)ky * im.hy;
+    cr = im.cxm + tx;
+    ci = im.cym + ty;
+}
+
+// ---------------------------------------------------------------------------
+// Dwell (Sec. 6): first k >= 1 with |z_k|^2 > 4, z_0 = 0, z_k = z_{k-1}^2 + c,
+// or D. One iteration is 3 multiplies and 4 adds, and the test reuses the
+// squares of the new z, which the next iteration needs anyway.
+// ---------------------------------------------------------------------------
+
+// Continue from the state after k iterations, testing after every iteration.
+__device__ __forceinline__ uint32_t dwell_from(double cr, double ci, uint32_t D, uint32_t k,
+                                               double zr, double zi, double zr2, double zi2) {
+    while (k < D) {
+        ++k;
+        const double zri = zr * zi;
+        zr = (zr2 - zi2) + cr;
+        zi = (zri + zri) + ci;
+        zr2 = zr * zr;
+        zi2 = zi * zi;
+        if (zr2 + zi2 > 4.0)
+            return k;
+    }
+    return D;
+}
+
+// Iterations between escape tests in the fast loop.
+constexpr uint32_t kStride = 16;
+
+// The fast loop runs kStride iterations without testing and then tests
+// !(|z|^2 <= 4), which also catches inf and NaN. When |c|^2 <= 3.99, once
+// |z_k|^2 > 4 has been seen the orbit grows strictly at every later step
+// (|z'| >= |z|^2 - |c| minus rounding, with 2 - |c| far above the rounding),
+// so a passing test at the end of a stretch proves that no escape happened
+// inside it. A failing test restarts the stretch from its saved start with a
+// test after every iteration, which finds the same first k as the plain loop.
+// Other c (|c| near or above 2, NaN) take the plain loop from the start.
+__device__ __forceinline__ uint32_t dwell(double cr, double ci, uint32_t D) {
+    double zr = 0.0, zi = 0.0, zr2 = 0.0, zi2 = 0.0;
+    uint32_t k = 0;
+    if (cr * cr + ci * ci <= 3.99) {
+        while (k + kStride <= D) {
+            const double szr = zr, szi = zi, szr2 = zr2, szi2 = zi2;
+#pragma unroll
+            for (uint32_t u = 0; u < kStride; ++u) {
+                const double zri = zr * zi;
+                zr = (zr2 - zi2) + cr;
+                zi = (zri + zri) + ci;
+                zr2 = zr * zr;
+                zi2 = zi * zi;
+            }
+            if (!(zr2 + zi2 <= 4.0)) {
+                zr = szr;
+                zi = szi;
+                zr2 = szr2;
+                zi2 = szi2;
+                break;
+            }
+            k += kStride;
+        }
+    }
+    return dwell_from(cr, ci, D, k, zr, zi, zr2, zi2);
+}
+
+// ---------------------------------------------------------------------------
+// Wave helpers (wave64).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v = min(v, (uint32_t)__shfl_xor((unsigned int)v, o));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v = max(v, (uint32_t)__shfl_xor((unsigned int)v, o));
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t lane_rank(unsigned long long mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Wave-wide values are made uniform with readfirstlane (the value of the
+// first active lane), never by branching on the lane index: a branch such as
+// `if (lane == 0)` ahead of a broadcast lets the optimiser route the other
+// lanes around it, and the broadcast then runs with the source lane missing.
+__device__ __forceinline__ uint32_t uniform(uint32_t v) {
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ bool first_lane() {
+    const uint32_t lane = __lane_id();
+    return lane == uniform(lane);
+}
+
+// One atomic per wave: every lane issues it and only the first active lane
+// contributes (a select, not a branch); every lane gets the old value.
+__device__ __forceinline__ uint32_t wave_add(uint32_t *p, uint32_t v) {
+    return uniform(atomicAdd(p, first_lane() ? v : 0u));
+}
+
+__device__ __forceinline__ void wave_add64(unsigned long long *p, unsigned long long v) {
+    atomicAdd(p, first_lane() ? v : 0ull);
+}
+
+__device__ __forceinline__ void wave_or(uint32_t *p, uint32_t v) {
+    atomicOr(p, first_lane() ? v : 0u);
+}
+
+__device__ __forceinline__ void wave_max(uint32_t *p, uint32_t v) {
+    atomicMax(p, first_lane() ? v : 0u);
+}
+
+// ---------------------------------------------------------------------------
+// Exhaustive image (Sec. 4.1): one lane per pixel. A 256-lane workgroup owns
+// a 16 x 16 tile; each wave a 16 x 4 strip of it.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void exhaustive_kernel(Image im) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wave = threadIdx.x / kWave;
+    const uint32_t px = blockIdx.x * 16 + (lane & 15);
+    const uint32_t py = blockIdx.y * 16 + wave * 4 + (lane >> 4);
+    if (px >= im.W || py >= im.H)
+        return;
+    double cr, ci;
+    pixel_c(im, px, py, cr, ci);
+    im.out[(size_t)py * im.W + px] = dwell(cr, ci, im.D);
+}
+
+// ---------------------------------------------------------------------------
+// Subdivision: one wave owns one region (the single-block-per-region scheme
+// of Sec. 4.3.1 with a wave64 as the block).
+// ---------------------------------------------------------------------------
+
+// The i-th pixel of the ring of [x, x+w) x [y, y+h): first row, last row,
+// then the first and last column between them.
+__device__ __forceinline__ void ring_pixel(uint32_t x, uint32_t y, uint32_t w, uint32_t h,
+                                           uint32_t i, uint32_t &px, uint32_t &py) {
+    if (h == 1) {
+        px = x + i;
+        py = y;
+    } else if (w == 1) {
+        px = x;
+        py = y + i;
+    } else if (i < w) {
+        px = x + i;
+        py = y;
+    } else if (i < 2 * w) {
+        px = x + (i - w);
+        py = y + h - 1;
+    } else {
+        const uint32_t j = i - 2 * w;
+        const uint32_t side = h - 2;
+        if (j < side) {
+            px = x;
+            py = y + 1 + j;
+        } else {
+            px = x + w - 1;
+            py = y + 1 + (j - side);
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t ring_size(uint32_t w, uint32_t h) {
+    return (w == 1 || h == 1) ? w * h : 2 * (w + h) - 4;
+}
+
+// Terminal work T: write v on every pixel of the region. Rows of 64 or more
+// pixels are written row by row, narrower regions several rows per pass.
+__device__ void fill_region(uint32_t *out, uint32_t W, uint32_t x, uint32_t y, uint32_t w,
+                            uint32_t h, uint32_t v, uint32_t lane) {
+    if (w >= kWave) {
+        for (uint32_t row = 0; row < h; ++row) {
+            uint32_t *p = out + (size_t)(y + row) * W + x;
+            for (uint32_t c = lane; c < w; c += kWave)
+                p[c] = v;
+        }
+    } else {
+        const uint32_t per = kWave / w;
+        const uint32_t lr = lane / w, lc = lane - lr * w;
+        if (lr < per)
+            for (uint32_t row = lr; row < h; row += per)
+                out[(size_t)(y + row) * W + x + lc] = v;
+    }
+}
+
+// Last-level work L: the dwell of every pixel of the region.
+__device__ unsigned long long leaf_region(const Image &im, uint32_t x, uint32_t y, uint32_t w,
+                                          uint32_t h, uint32_t lane) {
+    unsigned long long it = 0;
+    if (w >= kWave) {
+        for (uint32_t row = 0; row < h; ++row)
+            for (uint32_t c = lane; c < w; c += kWave) {
+                double cr, ci;
+                pixel_c(im, x + c, y + row, cr, ci);
+                const uint32_t d = dwell(cr, ci, im.D);
+                im.out[(size_t)(y + row) * im.W + x + c] = d;
+                it += d;
+            }
+    } else {
+        const uint32_t per = kWave / w;
+        const uint32_t lr = lane / w, lc = lane - lr * w;
+        if (lr < per)
+            for (uint32_t row = lr; row < h; row += per) {
+                double cr, ci;
+                pixel_c(im, x + lc, y + row, cr, ci);
+                const uint32_t d = dwell(cr, ci, im.D);
+                im.out[(size_t)(y + row) * im.W + x + lc] = d;
+                it += d;
+            }
+    }
+    return it;
+}
+
+__device__ __forceinline__ Image image_of(const SubdivArgs &a, uint32_t img) {
+    return a.table ? a.table[img] : a.single;
+}
+
+// S: append the non-empty pieces of the r x r floor partition of the region
+// to the next level (per-level form) or to the queue (persistent form), with
+// one atomic add per wave and per 64 children (Sec. 5.3.1).
+template <bool kQueue>
+__device__ void split_region(const SubdivArgs &a, uint32_t img, uint32_t x, uint32_t y,
+                             uint32_t w, uint32_t h, uint32_t r, uint32_t level, uint32_t lane) {
+    const uint32_t nchild = r * r;
+    const uint32_t tag = (a.epoch << 8) | (level + 1);
+    for (uint32_t base = 0; base < nchild; base += kWave) {
+        const uint32_t j = base + lane;
+        uint32_t cx0 = 0, cx1 = 0, cy0 = 0, cy1 = 0;
+        bool ok = false;
+        if (j < nchild) {
+            const uint32_t jx = j % r, jy = j / r;
+            cx0 = x + (uint32_t)(((uint64_t)jx * w) / r);
+            cx1 = x + (uint32_t)(((uint64_t)(jx + 1) * w) / r);
+            cy0 = y + (uint32_t)(((uint64_t)jy * h) / r);
+            cy1 = y + (uint32_t)(((uint64_t)(jy + 1) * h) / r);
+            ok = cx1 > cx0 && cy1 > cy0;
+        }
+        const unsigned long long mask = __ballot(ok);
+        const uint32_t n = (uint32_t)__popcll(mask);
+        if (n == 0)
+            continue;
+        const uint32_t slot0 = wave_add(kQueue ? &a.ctrl[kTail] : &a.ctrl[kCount + level + 1], n);
+        const bool fits = (uint64_t)slot0 + n <= a.cap;
+        if (fits) {
+            if (kQueue)
+                wave_add(&a.ctrl[kPending], n);
+        } else {
+            wave_or(&a.ctrl[kOverflow], 1u);
+            wave_or(&a.ctrl[kSticky], kErrOverflow);
+        }
+        if (ok && fits) {
+            const uint32_t slot = slot0 + lane_rank(mask);
+            if (kQueue) {
+                Region *e = a.queue + slot;
+                e->img = img;
+                e->xy = pack_xy(cx0, cy0);
+                e->wh = pack_wh(cx1 - cx0, cy1 - cy0);
+                __hip_atomic_store(&e->tag, tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                a.out[slot] = Region{img, pack_xy(cx0, cy0), pack_wh(cx1 - cx0, cy1 - cy0), tag};
+            }
+        }
+    }
+}
+
+// One region, by one wave: border query Q, then fill T, leaf L or split S
+// (Sec. 4.2.1).
+template <bool kQueue>
+__device__ void process_region(const SubdivArgs &a, const Region &R, uint32_t lane) {
+    const uint32_t img = uniform(R.img), xy = uniform(R.xy), wh = uniform(R.wh);
+    const uint32_t level = uniform(R.tag) & 0xffu;
+    const Image im = image_of(a, img);
+    const uint32_t x = xy & 0xffffu, y = xy >> 16;
+    const uint32_t w = (wh & 0xffffu) + 1, h = (wh >> 16) + 1;
+
+    // Q: dwell of every ring pixel, reduced to min and max over the wave.
+    const uint32_t nring = ring_size(w, h);
+    uint32_t vmin = 0xffffffffu, vmax = 0;
+    unsigned long long it = 0;
+    for (uint32_t i = lane; i < nring; i += kWave) {
+        uint32_t px, py;
+        ring_pixel(x, y, w, h, i, px, py);
+        double cr, ci;
+        pixel_c(im, px, py, cr, ci);
+        const uint32_t d = dwell(cr, ci, im.D);
+        vmin = min(vmin, d);
+        vmax = max(vmax, d);
+        it += d;
+    }
+    vmin = uniform(wave_min(vmin));
+    vmax = uniform(wave_max(vmax));
+    DevStats *st = a.stats;
+    if (st) {
+        it = wave_sum(it);
+        wave_add64(&st->regions[level], 1ull);
+        wave_add64(&st->iters_ring, it);
+        wave_max(&st->levels, level + 1);
+    }
+    if (vmin == vmax) {
+        fill_region(im.out, im.W, x, y, w, h, vmin, lane);
+        if (st)
+            wave_add64(&st->fills[level], 1ull);
+        return;
+    }
+    if (w <= im.B && h <= im.B) {
+        unsigned long long li = leaf_region(im, x, y, w, h, lane);
+        if (st) {
+            li = wave_sum(li);
+            wave_add64(&st->leaves[level], 1ull);
+            wave_add64(&st->iters_leaf, li);
+        }
+        return;
+    }
+    if (level + 1 >= kMaxLevels) {  // unreachable for valid sizes; never write past the tables
+        wave_or(&a.ctrl[kOverflow], 2u);
+        wave_or(&a.ctrl[kSticky], kErrOverflow);
+        return;
+    }
+    split_region<kQueue>(a, img, x, y, w, h, im.r, level, lane);
+    if (st)
+        wave_add64(&st->splits[level], 1ull);
+}
+
+// Per-level kernel: waves take the level's regions one at a time through an
+// atomic counter; the region count was written by the previous level.
+__global__ __launch_bounds__(kBlock) void level_kernel(SubdivArgs a) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t n = min(a.ctrl[kCount + a.level], a.cap);
+    for (;;) {
+        const uint32_t idx = wave_add(&a.ctrl[kClaim + a.level], 1u);
+        if (idx >= n)
+            break;
+        process_region<false>(a, a.in[idx], lane);
+    }
+}
+
+// Per-level kernel with the grid sized on the host to the level's region
+// count: wave i takes region i.
+__global__ __launch_bounds__(kBlock) void level_exact_kernel(SubdivArgs a, uint32_t n) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t idx = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    if (idx >= n)
+        return;
+    process_region<false>(a, a.in[idx], lane);
+}
+
+// Persistent kernel: every wave takes the next queue slot, waits until the
+// slot is published (its tag carries this launch's epoch), processes the
+// region and appends its children to the queue. `pending` counts regions
+// queued or in progress; a producer adds its children to it before it
+// removes itself, so pending reaches 0 only when no region is left or can
+// still be published, and then every waiting wave leaves.
+//
+// Waiting is cheap on purpose: the slot's tag and `pending` are read with
+// relaxed loads (no cache invalidation), with a growing pause between reads,
+// and a single acquire fence follows once the tag is seen. Every wait is also
+// bounded in wall-clock time: a wave that waits longer than a.wait_ticks of
+// the constant-rate clock records a timeout and leaves, so the grid always
+// drains.
+__device__ __forceinline__ void pause(uint32_t n) {
+    for (uint32_t i = 0; i < n; ++i)
+        __builtin_amdgcn_s_sleep(2);
+}
+
+__global__ __launch_bounds__(kBlock) void persistent_kernel(SubdivArgs a) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    uint32_t *ctrl = a.ctrl;
+    for (;;) {
+        // Every lane runs the wait; the values it reads are made uniform.
+        const uint32_t idx = wave_add(&ctrl[kHead], 1u);
+        const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+        uint32_t nap = 1, polls = 0;
+        bool ready = false;
+        for (;;) {
+            if (idx < a.cap) {
+                const uint32_t t = uniform(__hip_atomic_load(&a.queue[idx].tag, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT));
+                if ((t >> 8) == a.epoch) {
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    ready = true;
+                    break;
+                }
+            }
+            if ((++polls & 7) == 0 || idx >= a.cap) {
+                if (uniform(__hip_atomic_load(&ctrl[kPending], __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT)) == 0)
+                    break;
+                if (__builtin_amdgcn_s_memrealtime() - t0 > a.wait_ticks) {
+                    wave_or(&ctrl[kSticky], kErrTimeout);
+                    break;
+                }
+            }
+            pause(nap);
+            nap = min(nap * 2, 32u);
+        }
+        if (!ready)
+            return;
+        process_region<true>(a, a.queue[idx], lane);
+        wave_add(&ctrl[kPending], (uint32_t)-1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Set-up kernels.
+// ---------------------------------------------------------------------------
+// Clears the per-render control words (not the sticky error word) and the
+// counters.
+__global__ void reset_kernel(uint32_t *ctrl, DevStats *stats) {
+    for (uint32_t i = threadIdx.x; i < kSticky; i += blockDim.x)
+        ctrl[i] = 0;
+    if (stats) {
+        uint32_t *s = reinterpret_cast<uint32_t *>(stats);
+        for (uint32_t i = threadIdx.x; i < sizeof(DevStats) / 4; i += blockDim.x)
+            s[i] = 0;
+    }
+}
+
+// Level 0 (Sec. 4.2: G = g x g initial regions): the floor partition of each
+// image. Seed i belongs to the image whose seed range holds it.
+template <bool kQueue>
+__global__ void seed_kernel(SubdivArgs a, uint32_t nseeds) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        if (kQueue) {
+            a.ctrl[kTail] = nseeds;
+            a.ctrl[kPending] = nseeds;
+        } else {
+            a.ctrl[kCount] = nseeds;
+        }
+    }
+    if (i >= nseeds)
+        return;
+    uint32_t img = 0, local = i;
+    if (a.table) {
+        uint32_t lo = 0, hi = a.nimg;  // find seed_base[lo] <= i < seed_base[lo+1]
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) / 2;
+            if (a.seed_base[mid] <= i)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        img = lo;
+        local = i - a.seed_base[img];
+    }
+    const Image im = image_of(a, img);
+    const uint32_t g = im.g;
+    const uint32_t jx = local % g, jy = local / g;
+    const uint32_t x0 = (uint32_t)(((uint64_t)jx * im.W) / g);
+    const uint32_t x1 = (uint32_t)(((uint64_t)(jx + 1) * im.W) / g);
+    const uint32_t y0 = (uint32_t)(((uint64_t)jy * im.H) / g);
+    const uint32_t y1 = (uint32_t)(((uint64_t)(jy + 1) * im.H) / g);
+    const Region e{img, pack_xy(x0, y0), pack_wh(x1 - x0, y1 - y0), a.epoch << 8};
+    if (kQueue)
+        a.queue[i] = e;
+    else
+        a.out[i] = e;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+hipError_t launch_exhaustive(const Image &im, hipStream_t s) {
+    dim3 grid((im.W + 15) / 16, (im.H + 15) / 16);
+    hipLaunchKernelGGL(exhaustive_kernel, grid, dim3(kBlock), 0, s, im);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset(uint32_t *ctrl, DevStats *stats, hipStream_t s) {
+    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(kBlock), 0, s, ctrl, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed_levels(const SubdivArgs &a, uint32_t nseeds, hipStream_t s) {
+    const uint32_t blocks = (nseeds + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(seed_kernel<false>, dim3(blocks ? blocks : 1), dim3(kBlock), 0, s, a, nseeds);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed_queue(const SubdivArgs &a, uint32_t nseeds, hipStream_t s) {
+    const uint32_t blocks = (nseeds + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(seed_kernel<true>, dim3(blocks ? blocks : 1), dim3(kBlock), 0, s, a, nseeds);
+    return hipGetLastError();
+}
+
+hipError_t launch_level(const SubdivArgs &a, uint32_t grid_blocks, hipStream_t s) {
+    hipLaunchKernelGGL(level_kernel, dim3(grid_blocks), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_level_exact(const SubdivArgs &a, uint32_t nregions, hipStream_t s) {
+    const uint32_t blocks = (nregions + kWavesPerBlock - 1) / kWavesPerBlock;
+    hipLaunchKernelGGL(level_exact_kernel, dim3(blocks), dim3(kBlock), 0, s, a, nregions);
+    return hipGetLastError();
+}
+
+hipError_t launch_persistent(const SubdivArgs &a, uint32_t grid_blocks, hipStream_t s) {
+    hipLaunchKernelGGL(persistent_kernel, dim3(grid_blocks), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t occupancy_level(int *blocks_per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, level_kernel, kBlock, 0);
+}
+
+hipError_t occupancy_persistent(int *blocks_per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, persistent_kernel, kBlock, 0);
+}
+
+}  // namespace ask

@@ -1,0 +1,83 @@
+"""The C-ABI library loads, exports every symbol include/ask.h declares, and its
+host-only logic (argument checks, mapping constants, level count) is right.
+No kernel is launched here."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from workloads import Window, random_params, random_windows
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def ask():
+    from paper_2206_02255_amd import ask
+    return ask
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "ask.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ask_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(ask):
+    names = declared_functions()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(ask.lib, n), n
+        assert n in ask.SIGNATURES, n
+
+
+def test_status_strings(ask):
+    for s in (0, -1, -2, -3, -4, -5, -6):
+        assert ask.status_str(s)
+
+
+def test_mapping_equals_oracle_bit_for_bit(ask, ref):
+    for w in random_windows(1, 50) + [Window(-1.5, 0.5, -1.0, 1.0, 16384, 16384, 2048)]:
+        assert ask.ask_mapping(ask.window(w)) == ref.mapping(w)
+
+
+def test_validation(ask):
+    good = ask.window(Window(-1.5, 0.5, -1.0, 1.0, 64, 48, 100))
+    assert ask.ask_validate(good) == 0
+    assert ask.ask_validate(good, ask.params(4, 2, 8)) == 0
+    for g, r, B in [(0, 2, 8), (49, 2, 8), (4, 1, 8), (4, 1025, 8), (4, 2, 0)]:
+        assert ask.ask_validate(good, ask.params(g, r, B)) == ask.EINVAL
+    assert ask.ask_validate(good, ask.params(4, 2, 8, form=7)) == ask.EINVAL
+    for w in [Window(0.5, -1.5, -1, 1, 8, 8, 10), Window(-1, 1, -1, 1, 0, 8, 10),
+              Window(-1, 1, -1, 1, 8, 8, 0), Window(-1, float("inf"), -1, 1, 8, 8, 10),
+              Window(-1, 1, -1, 1, 8, 65537, 10), Window(-1, 1, -1, 1, 8, 8, 2**31)]:
+        assert ask.ask_validate(ask.window(w)) == ask.EINVAL
+    bad = ask.window(Window(-1, 1, -1, 1, 8, 8, 10))
+    bad.reserved = 1
+    assert ask.ask_validate(bad) == ask.EINVAL
+
+
+def test_level_count_bounds_the_oracle_depth(ask, ref):
+    # The host fixes the number of level kernels from (W, H, g, r, B) alone;
+    # it must never be below the depth the subdivision actually reaches.
+    for i, w in enumerate(random_windows(7, 20, max_side=80, max_dwell=150)):
+        for p in random_params(200 + i, w, 4):
+            n = ask.ask_level_count(ask.window(w), ask.params(p.g, p.r, p.B))
+            _, st = ref.subdiv(w, p.g, p.r, p.B)
+            assert st["levels"] <= n
+    # the paper's window: the boundary crosses every level down to B
+    w = Window(-1.5, 0.5, -1.0, 1.0, 1024, 1024, 512)
+    n = ask.ask_level_count(ask.window(w), ask.params(4, 2, 32))
+    _, st = ref.subdiv(w, 4, 2, 32)
+    assert n == st["levels"] == 4
+
+
+def test_create_without_device_reports_device_error(ask):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(ask.AskError) as e:
+        ask.ask_create(0)
+    assert e.value.status == ask.EDEVICE

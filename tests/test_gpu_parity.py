@@ -1,0 +1,233 @@
+"""GPU parity: images from the C ABI equal the CPU oracle's bit for bit.
+
+Dwell images are integers, so the bar is exact equality of every pixel (and
+of the work counters) against the oracle on the same seeded inputs: small
+ragged windows that span several tiles and regions, the 1024 x 1024 paper
+window, a 4096 x 4096 window, and sampled pixels of the 16384 x 16384 window.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from workloads import LARGE, SMALL, SMALL_PARAMS, Window, paper_window, random_params, random_windows
+
+pytestmark = pytest.mark.gpu
+
+FORMS = ("levels", "levels_readback", "persistent")
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    from paper_2206_02255_amd import ask
+    assert torch.cuda.is_available()
+    ctx = ask.ask_create(0)
+    yield ask, ctx, torch
+    ask.ask_destroy(ctx)
+
+
+def _out(torch, w):
+    return torch.zeros(w.H * w.W, dtype=torch.int32, device="cuda")
+
+
+def _host(torch, t, w):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().view(np.uint32).reshape(w.H, w.W)
+
+
+def gpu_exhaustive(gpu, w):
+    ask, ctx, torch = gpu
+    out = _out(torch, w)
+    ask.ask_dwell_exhaustive(ctx, ask.window(w), out.data_ptr(),
+                             torch.cuda.current_stream().cuda_stream)
+    return _host(torch, out, w)
+
+
+def gpu_subdiv(gpu, w, g, r, B, form, stats=True):
+    ask, ctx, torch = gpu
+    out = _out(torch, w)
+    st = ask.ask_dwell_subdiv(ctx, ask.window(w), ask.params(g, r, B, form), out.data_ptr(),
+                              torch.cuda.current_stream().cuda_stream, want_stats=stats)
+    return _host(torch, out, w), st
+
+
+def assert_same_stats(st, ref_st):
+    n = ref_st["levels"]
+    assert st["levels"] == n
+    for k in ("regions", "fills", "splits", "leaves"):
+        assert st[k][:n] == ref_st[k][:n], k
+    assert st["iters_ring"] == ref_st["iters_ring"]
+    assert st["iters_leaf"] == ref_st["iters_leaf"]
+    assert st["overflow"] == 0
+
+
+EDGE_WINDOWS = [
+    Window(-1.5, 0.5, -1.0, 1.0, 1, 1, 100),
+    Window(-1.5, 0.5, -1.0, 1.0, 1, 77, 100),
+    Window(-1.5, 0.5, -1.0, 1.0, 93, 1, 100),
+    Window(-1.5, 0.5, -1.0, 1.0, 17, 300, 1),    # D = 1
+    Window(-1.5, 0.5, -1.0, 1.0, 130, 70, 15),   # D below the test stride
+    Window(-1.5, 0.5, -1.0, 1.0, 130, 70, 16),
+    Window(-1.5, 0.5, -1.0, 1.0, 130, 70, 17),
+]
+
+
+def adversarial_windows():
+    """Windows where the escape test is delicate: around c = -2 (orbits that
+    hover at |z| = 2), on the circle |c| = 2, and across |c|^2 = 3.99, where
+    the fast loop hands over to the plain one."""
+    out = []
+    for span in (1e-15, 1e-12, 1e-8, 1e-4):
+        out.append(Window(-2 - span, -2 + span, -span, span, 67, 61, 3000))
+    for th in np.linspace(0.1, math.pi, 9):
+        cx, cy = 2 * math.cos(th), 2 * math.sin(th)
+        for span in (1e-13, 1e-6):
+            out.append(Window(cx - span, cx + span, cy - span, cy + span, 33, 35, 500))
+    rad = math.sqrt(3.99)
+    for th in (0.3, 1.7, 2.9, 3.1):
+        cx, cy = rad * math.cos(th), rad * math.sin(th)
+        out.append(Window(cx - 1e-9, cx + 1e-9, cy - 1e-9, cy + 1e-9, 40, 40, 2000))
+    return out
+
+
+def test_exhaustive_edge_windows(gpu, ref):
+    for w in EDGE_WINDOWS:
+        print("exhaustive", w, flush=True)
+        assert np.array_equal(gpu_exhaustive(gpu, w), ref.exhaustive(w)[0])
+
+
+def test_exhaustive_adversarial_windows(gpu, ref):
+    for w in adversarial_windows():
+        print("exhaustive", w, flush=True)
+        assert np.array_equal(gpu_exhaustive(gpu, w), ref.exhaustive(w)[0])
+
+
+def test_exhaustive_random_windows(gpu, ref):
+    for w in random_windows(31, 40, max_side=200, max_dwell=3000):
+        print("exhaustive", w, flush=True)
+        assert np.array_equal(gpu_exhaustive(gpu, w), ref.exhaustive(w)[0])
+
+
+def test_exhaustive_small_paper_window(gpu, ref):
+    img = gpu_exhaustive(gpu, SMALL)
+    want, iters = ref.exhaustive(SMALL)
+    assert np.array_equal(img, want)
+    assert int(img.astype(np.uint64).sum()) == iters
+
+
+def test_exhaustive_4096(gpu, ref):
+    w = paper_window(4096, 2048)
+    assert np.array_equal(gpu_exhaustive(gpu, w), ref.exhaustive(w)[0])
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_subdiv_edge_windows(gpu, ref, form):
+    for w in EDGE_WINDOWS:
+        for g, r, B in [(1, 2, 1), (1, 3, 4), (min(w.W, w.H), 2, 2)]:
+            print(form, w, g, r, B, flush=True)
+            img, st = gpu_subdiv(gpu, w, g, r, B, form)
+            want, ref_st = ref.subdiv(w, g, r, B)
+            assert np.array_equal(img, want)
+            assert_same_stats(st, ref_st)
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_subdiv_random_windows(gpu, ref, form):
+    for i, w in enumerate(random_windows(41, 25, max_side=160, max_dwell=2000)):
+        for p in random_params(300 + i, w, 3):
+            print(form, w, p, flush=True)
+            img, st = gpu_subdiv(gpu, w, p.g, p.r, p.B, form)
+            want, ref_st = ref.subdiv(w, p.g, p.r, p.B)
+            assert np.array_equal(img, want)
+            assert_same_stats(st, ref_st)
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_subdiv_small_paper_window(gpu, ref, form):
+    p = SMALL_PARAMS
+    img, st = gpu_subdiv(gpu, SMALL, p.g, p.r, p.B, form)
+    want, ref_st = ref.subdiv(SMALL, p.g, p.r, p.B)
+    assert np.array_equal(img, want)
+    assert_same_stats(st, ref_st)
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("g,r,B", [(32, 4, 16), (16, 2, 32), (2, 8, 128), (64, 2, 16)])
+def test_subdiv_4096(gpu, ref, form, g, r, B):
+    w = paper_window(4096, 2048)
+    img, st = gpu_subdiv(gpu, w, g, r, B, form)
+    want, ref_st = ref.subdiv(w, g, r, B)
+    assert np.array_equal(img, want)
+    assert_same_stats(st, ref_st)
+
+
+def test_subdiv_without_stats_equals_with_stats(gpu):
+    w = paper_window(2048, 1024)
+    for form in FORMS:
+        a, _ = gpu_subdiv(gpu, w, 8, 2, 16, form, stats=True)
+        b, _ = gpu_subdiv(gpu, w, 8, 2, 16, form, stats=False)
+        assert np.array_equal(a, b)
+
+
+def test_persistent_repeated_calls(gpu, ref):
+    # Queue slots are reused across calls; tags of older calls must never be
+    # taken for new entries.
+    ws = random_windows(51, 6, max_side=120, max_dwell=600)
+    for rep in range(3):
+        for w in ws:
+            img, _ = gpu_subdiv(gpu, w, 2, 2, 4, "persistent", stats=False)
+            assert np.array_equal(img, ref.subdiv(w, 2, 2, 4)[0])
+
+
+@pytest.mark.parametrize("form", ["levels", "persistent"])
+def test_large_paper_window_sampled(gpu, ref, form):
+    # 16384 x 16384, D = 2048: sampled pixels against the oracle's tree
+    # descent, plus the counters that hold at any size.
+    w = LARGE
+    g, r, B = 32, 4, 16
+    img, st = gpu_subdiv(gpu, w, g, r, B, form)
+    rng = np.random.default_rng(77)
+    px = rng.integers(0, w.W, 150)
+    py = rng.integers(0, w.H, 150)
+    assert np.array_equal(img[py, px], ref.subdiv_pixels(w, g, r, B, px, py))
+    assert st["overflow"] == 0
+    assert st["regions"][0] == g * g
+    for lv in range(st["levels"] - 1):
+        assert st["regions"][lv + 1] <= st["splits"][lv] * r * r
+        assert st["regions"][lv] == st["fills"][lv] + st["leaves"][lv] + st["splits"][lv]
+    assert (img >= 1).all() and (img <= w.D).all()
+    # the window is symmetric about the real axis and 16384 = 32 * 4^3 * 8
+    assert np.array_equal(img[:64], img[::-1][:64])
+
+
+def test_large_exhaustive_sampled(gpu, ref):
+    w = LARGE
+    img = gpu_exhaustive(gpu, w)
+    rng = np.random.default_rng(78)
+    px = rng.integers(0, w.W, 400)
+    py = rng.integers(0, w.H, 400)
+    assert np.array_equal(img[py, px], ref.dwell_pixels(w, px, py))
+    assert np.array_equal(img[:32], img[::-1][:32])
+
+
+def test_persistent_wait_limit_reports_timeout(gpu, ref):
+    # Host-forced failure: with a zero wait limit every wave that has to wait
+    # records a timeout and leaves; the render reports ASK_ETIMEOUT, and the
+    # next render on the same context is whole again.
+    ask, ctx, torch = gpu
+    w = paper_window(512, 256)
+    stream = torch.cuda.current_stream().cuda_stream
+    out = _out(torch, w)
+    ask.ask_set_wait_limit(ctx, 0.0)
+    try:
+        ask.ask_dwell_subdiv(ctx, ask.window(w), ask.params(2, 2, 8, "persistent"),
+                             out.data_ptr(), stream)
+        with pytest.raises(ask.AskError) as e:
+            ask.ask_synchronize(ctx, stream)
+        assert e.value.status == ask.ETIMEOUT
+    finally:
+        ask.ask_set_wait_limit(ctx, 10.0)
+    img, _ = gpu_subdiv(gpu, w, 2, 2, 8, "persistent")
+    assert np.array_equal(img, ref.subdiv(w, 2, 2, 8)[0])
+    ask.ask_synchronize(ctx, stream)
