@@ -155,6 +155,17 @@ ask_status ask_dwell_subdiv(ask_ctx *ctx, const ask_window *win,
  * reports either error has left an invalid image. */
 ask_status ask_synchronize(ask_ctx *ctx, void *stream);
 
+/* Record HIP events, on the render's stream, around the dominant kernels of
+ * later renders on this context (on != 0), or stop (on == 0). Dominant
+ * kernels: the exhaustive kernel; the level kernels, from the first one's
+ * start to the last one's end; the persistent kernel. Set-up kernels (counter
+ * reset, level-0 seeding) are outside the events. */
+ask_status ask_enable_timing(ask_ctx *ctx, int on);
+
+/* Device time, in milliseconds, of the dominant kernels of the last render
+ * timed on this context. Waits for that render; ASK_EINVAL if there is none. */
+ask_status ask_last_kernel_ms(ask_ctx *ctx, float *ms);
+
 /* Longest time, in seconds (0 to 3600, default 10), that one wave of the
  * persistent kernel waits for a region before it records ASK_ETIMEOUT and
  * leaves. This bounds every wait of the kernel, so its grid always drains;

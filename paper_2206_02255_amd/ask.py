@@ -69,6 +69,8 @@ SIGNATURES = {
                                    C.POINTER(ask_stats)]),
     "ask_synchronize": (C.c_int, [_P, _P]),
     "ask_set_wait_limit": (C.c_int, [_P, C.c_double]),
+    "ask_enable_timing": (C.c_int, [_P, C.c_int]),
+    "ask_last_kernel_ms": (C.c_int, [_P, C.POINTER(C.c_float)]),
 }
 
 
@@ -154,3 +156,13 @@ def ask_synchronize(ctx, stream=0):
 
 def ask_set_wait_limit(ctx, seconds):
     _check(lib.ask_set_wait_limit(ctx, float(seconds)), ctx)
+
+
+def ask_enable_timing(ctx, on=True):
+    _check(lib.ask_enable_timing(ctx, 1 if on else 0), ctx)
+
+
+def ask_last_kernel_ms(ctx):
+    ms = C.c_float()
+    _check(lib.ask_last_kernel_ms(ctx, C.byref(ms)), ctx)
+    return ms.value

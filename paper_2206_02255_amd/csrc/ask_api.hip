@@ -27,6 +27,9 @@ struct ask_ctx {
     uint32_t epoch = 0;                   // 24-bit launch counter for queue tags
     double wait_limit_s = 10.0;           // persistent kernel: longest wait of one wave
     double clock_hz = 1e8;                // rate of the device's constant clock
+    bool timing = false;                  // record events around the dominant kernels
+    bool timed = false;                   // the events hold a render
+    hipEvent_t ev[2] = {nullptr, nullptr};
     char err[512] = {0};
 };
 
@@ -212,6 +215,14 @@ ask_status read_stats(ask_ctx *ctx, hipStream_t s, ask_stats *out) {
     return st;
 }
 
+hipError_t mark(ask_ctx *ctx, int which, hipStream_t s) {
+    if (!ctx->timing)
+        return hipSuccess;
+    if (which == 1)
+        ctx->timed = true;
+    return hipEventRecord(ctx->ev[which], s);
+}
+
 }  // namespace
 
 extern "C" {
@@ -277,6 +288,10 @@ ask_status ask_create(ask_ctx **out, int device) {
     if (e == hipSuccess)
         e = hipMemset(ctx->ctrl, 0, kCtrlWords * sizeof(uint32_t));
     if (e == hipSuccess)
+        e = hipEventCreate(&ctx->ev[0]);
+    if (e == hipSuccess)
+        e = hipEventCreate(&ctx->ev[1]);
+    if (e == hipSuccess)
         e = occupancy_level(&ctx->occ_level);
     if (e == hipSuccess)
         e = occupancy_persistent(&ctx->occ_persistent);
@@ -308,6 +323,10 @@ ask_status ask_destroy(ask_ctx *ctx) {
         (void)hipFree(ctx->lvq[0]);
         (void)hipFree(ctx->lvq[1]);
         (void)hipFree(ctx->queue);
+        if (ctx->ev[0])
+            (void)hipEventDestroy(ctx->ev[0]);
+        if (ctx->ev[1])
+            (void)hipEventDestroy(ctx->ev[1]);
     }
     delete ctx;
     return ASK_OK;
@@ -321,7 +340,11 @@ ask_status ask_dwell_exhaustive(ask_ctx *ctx, const ask_window *win, uint32_t *d
         return fail(ctx, ASK_EINVAL, "invalid window or output%s", nullptr);
     DeviceGuard guard(ctx->device);
     const Image im = make_image(win, nullptr, d_out);
-    hipError_t e = launch_exhaustive(im, (hipStream_t)stream);
+    hipError_t e = mark(ctx, 0, (hipStream_t)stream);
+    if (e == hipSuccess)
+        e = launch_exhaustive(im, (hipStream_t)stream);
+    if (e == hipSuccess)
+        e = mark(ctx, 1, (hipStream_t)stream);
     if (e != hipSuccess)
         return hip_fail(ctx, e, "exhaustive kernel launch");
     return ASK_OK;
@@ -390,7 +413,11 @@ ask_status ask_dwell_subdiv(ask_ctx *ctx, const ask_window *win, const ask_param
         a.wait_ticks = (uint64_t)(ctx->wait_limit_s * ctx->clock_hz);
         e = launch_seed_queue(a, nseeds, s);
         if (e == hipSuccess)
+            e = mark(ctx, 0, s);
+        if (e == hipSuccess)
             e = launch_persistent(a, (uint32_t)(ctx->cus * ctx->occ_persistent), s);
+        if (e == hipSuccess)
+            e = mark(ctx, 1, s);
         if (e != hipSuccess)
             return hip_fail(ctx, e, "persistent launch");
     } else {
@@ -398,6 +425,8 @@ ask_status ask_dwell_subdiv(ask_ctx *ctx, const ask_window *win, const ask_param
         a.epoch = 0;
         a.out = ctx->lvq[0];
         e = launch_seed_levels(a, nseeds, s);
+        if (e == hipSuccess)
+            e = mark(ctx, 0, s);
         if (e != hipSuccess)
             return hip_fail(ctx, e, "seed kernel launch");
         const uint32_t resident = (uint32_t)(ctx->cus * ctx->occ_level);
@@ -425,9 +454,34 @@ ask_status ask_dwell_subdiv(ask_ctx *ctx, const ask_window *win, const ask_param
             if (e != hipSuccess)
                 return hip_fail(ctx, e, "level kernel launch");
         }
+        e = mark(ctx, 1, s);
+        if (e != hipSuccess)
+            return hip_fail(ctx, e, "hipEventRecord");
     }
     if (stats || may_overflow)
         return read_stats(ctx, s, stats);
+    return ASK_OK;
+}
+
+ask_status ask_enable_timing(ask_ctx *ctx, int on) {
+    if (!ctx)
+        return ASK_EINVAL;
+    ctx->timing = on != 0;
+    ctx->timed = false;
+    return ASK_OK;
+}
+
+ask_status ask_last_kernel_ms(ask_ctx *ctx, float *ms) {
+    if (!ctx || !ms)
+        return ASK_EINVAL;
+    if (!ctx->timed)
+        return fail(ctx, ASK_EINVAL, "no timed render on this context%s", nullptr);
+    DeviceGuard guard(ctx->device);
+    hipError_t e = hipEventSynchronize(ctx->ev[1]);
+    if (e == hipSuccess)
+        e = hipEventElapsedTime(ms, ctx->ev[0], ctx->ev[1]);
+    if (e != hipSuccess)
+        return hip_fail(ctx, e, "hipEventElapsedTime");
     return ASK_OK;
 }
 

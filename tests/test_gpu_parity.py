@@ -10,7 +10,8 @@ import math
 import numpy as np
 import pytest
 
-from workloads import LARGE, SMALL, SMALL_PARAMS, Window, paper_window, random_params, random_windows
+from workloads import (LARGE, LARGE_DEFAULT, LARGE_DEFAULT_FORM, SMALL, SMALL_PARAMS, Window,
+                       paper_window, random_params, random_windows)
 
 pytestmark = pytest.mark.gpu
 
@@ -180,12 +181,14 @@ def test_persistent_repeated_calls(gpu, ref):
             assert np.array_equal(img, ref.subdiv(w, 2, 2, 4)[0])
 
 
-@pytest.mark.parametrize("form", ["levels", "persistent"])
-def test_large_paper_window_sampled(gpu, ref, form):
+@pytest.mark.parametrize("form,g,r,B", [
+    ("levels", 32, 4, 16), ("persistent", 32, 4, 16),
+    (LARGE_DEFAULT_FORM, LARGE_DEFAULT.g, LARGE_DEFAULT.r, LARGE_DEFAULT.B)])
+def test_large_paper_window_sampled(gpu, ref, form, g, r, B):
     # 16384 x 16384, D = 2048: sampled pixels against the oracle's tree
-    # descent, plus the counters that hold at any size.
+    # descent, plus the counters that hold at any size (the last case is the
+    # benchmark's launch configuration).
     w = LARGE
-    g, r, B = 32, 4, 16
     img, st = gpu_subdiv(gpu, w, g, r, B, form)
     rng = np.random.default_rng(77)
     px = rng.integers(0, w.W, 150)
@@ -197,7 +200,8 @@ def test_large_paper_window_sampled(gpu, ref, form):
         assert st["regions"][lv + 1] <= st["splits"][lv] * r * r
         assert st["regions"][lv] == st["fills"][lv] + st["leaves"][lv] + st["splits"][lv]
     assert (img >= 1).all() and (img <= w.D).all()
-    # the window is symmetric about the real axis and 16384 = 32 * 4^3 * 8
+    # the window is symmetric about the real axis and every partition of
+    # 16384 used here is exact, so the image is too
     assert np.array_equal(img[:64], img[::-1][:64])
 
 

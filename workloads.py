@@ -57,6 +57,9 @@ SMALL_PARAMS = Params(4, 2, 32)
 LARGE = paper_window(16384, 2048)
 LARGE_SWEEP = [Params(g, r, B) for g in (2, 4, 8, 16, 32)
                for r in (2, 4, 8) for B in (16, 32, 64, 128)]
+# The benchmark's launch configuration for the large image.
+LARGE_DEFAULT = Params(64, 2, 32)
+LARGE_DEFAULT_FORM = "persistent"
 
 
 def random_windows(seed, count, max_side=96, max_dwell=300):
