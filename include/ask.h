@@ -148,6 +148,21 @@ ask_status ask_dwell_subdiv(ask_ctx *ctx, const ask_window *win,
                             const ask_params *params, uint32_t *d_out,
                             void *stream, ask_stats *stats);
 
+/* A batch of n >= 1 subdivision images rendered by one sequence of launches
+ * over one shared region queue: one seeding pass for all images, then one
+ * persistent kernel (or one kernel per level) whose waves take regions of
+ * any image. Each image i is the image ask_dwell_subdiv would give for
+ * wins[i] and its parameters, bit for bit. params: nparams == 1 (shared by
+ * all images) or nparams == n (one per image); every entry must have the
+ * same form. d_outs[i]: device memory, wins[i].W * wins[i].H uint32,
+ * caller-owned; images must not overlap. stats (optional) sums the counters
+ * over the batch and makes the call wait, as for ask_dwell_subdiv. The image
+ * table is staged through context-owned pinned memory; the call returns
+ * once the staging buffer is free for its copy. */
+ask_status ask_dwell_batch(ask_ctx *ctx, uint32_t n, const ask_window *wins,
+                           const ask_params *params, uint32_t nparams,
+                           uint32_t *const *d_outs, void *stream, ask_stats *stats);
+
 /* Wait for `stream`, then report the errors the kernels recorded on this
  * context since the last check: ASK_ETIMEOUT when a persistent wave gave up
  * waiting (see ask_set_wait_limit), else ASK_EOVERFLOW when a queue ran out

@@ -272,8 +272,10 @@ static void process(const sd_ctx *c, sd_local *L, const rect *R, uint32_t level,
     L->st.regions[level] += 1;
     if (level + 1 > L->st.levels)
         L->st.levels = level + 1;
+    const uint64_t ring_before = L->st.iters_ring;
     int uniform = scan_ring(c, L, R, &v);
     if (uniform) {
+        L->st.iters_ring_filled += L->st.iters_ring - ring_before;
         /* T: write the common ring value on every pixel of the region. */
         for (uint32_t py = R->y; py < R->y + R->h; ++py)
             for (uint32_t px = R->x; px < R->x + R->w; ++px)
@@ -400,6 +402,7 @@ static void add_stats(askref_stats *a, const askref_stats *b)
     a->iters_leaf += b->iters_leaf;
     a->iters_ring_new += b->iters_ring_new;
     a->iters_leaf_inner += b->iters_leaf_inner;
+    a->iters_ring_filled += b->iters_ring_filled;
 }
 
 int64_t askref_subdiv(double x0, double x1, double y0, double y1,

@@ -41,6 +41,7 @@ typedef struct askref_stats {
     uint64_t iters_leaf;                   /* sum of dwell over every leaf pixel */
     uint64_t iters_ring_new;               /* ring pixels that are not on the parent's ring */
     uint64_t iters_leaf_inner;             /* leaf pixels that are not on the leaf's own ring */
+    uint64_t iters_ring_filled;            /* sum of dwell over the rings of filled regions */
 } askref_stats;
 
 /* One scanned region, for invariant checks. kind: 1 fill, 2 leaf, 3 split. */

@@ -25,13 +25,15 @@ class Stats(C.Structure):
         ("ring_px", C.c_uint64), ("leaf_px", C.c_uint64), ("fill_px", C.c_uint64),
         ("iters_ring", C.c_uint64), ("iters_leaf", C.c_uint64),
         ("iters_ring_new", C.c_uint64), ("iters_leaf_inner", C.c_uint64),
+        ("iters_ring_filled", C.c_uint64),
     ]
 
     def as_dict(self):
         n = self.levels
         d = {k: getattr(self, k) for k in ("levels", "ring_px", "leaf_px", "fill_px",
                                             "iters_ring", "iters_leaf",
-                                            "iters_ring_new", "iters_leaf_inner")}
+                                            "iters_ring_new", "iters_leaf_inner",
+                                            "iters_ring_filled")}
         for k in ("regions", "fills", "splits", "leaves"):
             d[k] = list(getattr(self, k)[:n])
         d["iters_alg"] = self.iters_ring + self.iters_leaf

@@ -67,6 +67,8 @@ SIGNATURES = {
     "ask_dwell_exhaustive": (C.c_int, [_P, C.POINTER(ask_window), _P, _P]),
     "ask_dwell_subdiv": (C.c_int, [_P, C.POINTER(ask_window), C.POINTER(ask_params), _P, _P,
                                    C.POINTER(ask_stats)]),
+    "ask_dwell_batch": (C.c_int, [_P, C.c_uint32, C.POINTER(ask_window), C.POINTER(ask_params),
+                                  C.c_uint32, C.POINTER(C.c_void_p), _P, C.POINTER(ask_stats)]),
     "ask_synchronize": (C.c_int, [_P, _P]),
     "ask_set_wait_limit": (C.c_int, [_P, C.c_double]),
     "ask_enable_timing": (C.c_int, [_P, C.c_int]),
@@ -166,3 +168,18 @@ def ask_last_kernel_ms(ctx):
     ms = C.c_float()
     _check(lib.ask_last_kernel_ms(ctx, C.byref(ms)), ctx)
     return ms.value
+
+
+def ask_dwell_batch(ctx, wins, prms, d_outs, stream=0, want_stats=False):
+    """wins: sequence of ask_window; prms: one ask_params or one per window;
+    d_outs: device pointers (ints)."""
+    n = len(wins)
+    if isinstance(prms, ask_params):
+        prms = [prms]
+    W = (ask_window * n)(*wins)
+    P = (ask_params * len(prms))(*prms)
+    O = (C.c_void_p * n)(*[int(p) for p in d_outs])
+    st = ask_stats() if want_stats else None
+    _check(lib.ask_dwell_batch(ctx, n, W, P, len(prms), O, _P(stream),
+                               C.byref(st) if st is not None else None), ctx)
+    return st.as_dict() if st is not None else None

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "ask_internal.hpp"
 
@@ -30,6 +31,13 @@ struct ask_ctx {
     bool timing = false;                  // record events around the dominant kernels
     bool timed = false;                   // the events hold a render
     hipEvent_t ev[2] = {nullptr, nullptr};
+    // Batches: image table and level-0 seed offsets on the device, staged
+    // through pinned host memory whose last copy `staged` marks.
+    void *table = nullptr;
+    size_t table_bytes = 0;
+    void *staging = nullptr;
+    size_t staging_bytes = 0;
+    hipEvent_t staged = nullptr;
     char err[512] = {0};
 };
 
@@ -292,6 +300,8 @@ ask_status ask_create(ask_ctx **out, int device) {
     if (e == hipSuccess)
         e = hipEventCreate(&ctx->ev[1]);
     if (e == hipSuccess)
+        e = hipEventCreateWithFlags(&ctx->staged, hipEventDisableTiming);
+    if (e == hipSuccess)
         e = occupancy_level(&ctx->occ_level);
     if (e == hipSuccess)
         e = occupancy_persistent(&ctx->occ_persistent);
@@ -327,6 +337,10 @@ ask_status ask_destroy(ask_ctx *ctx) {
             (void)hipEventDestroy(ctx->ev[0]);
         if (ctx->ev[1])
             (void)hipEventDestroy(ctx->ev[1]);
+        if (ctx->staged)
+            (void)hipEventDestroy(ctx->staged);
+        (void)hipFree(ctx->table);
+        (void)hipHostFree(ctx->staging);
     }
     delete ctx;
     return ASK_OK;
@@ -350,25 +364,39 @@ ask_status ask_dwell_exhaustive(ask_ctx *ctx, const ask_window *win, uint32_t *d
     return ASK_OK;
 }
 
-ask_status ask_dwell_subdiv(ask_ctx *ctx, const ask_window *win, const ask_params *params,
-                            uint32_t *d_out, void *stream, ask_stats *stats) {
-    if (!ctx)
-        return ASK_EINVAL;
-    if (ask_validate(win, params) != ASK_OK || !params || !d_out)
-        return fail(ctx, ASK_EINVAL, "invalid window, parameters or output%s", nullptr);
-    DeviceGuard guard(ctx->device);
-    hipStream_t s = (hipStream_t)stream;
-    const uint32_t levels = level_count(win->W, win->H, params->g, params->r, params->B);
-    if (levels > (uint32_t)kMaxLevels)
-        return fail(ctx, ASK_EINVAL, "too many levels%s", nullptr);
-    const uint64_t pixels = (uint64_t)win->W * win->H;
-    uint64_t widest = 0, total = 0;
-    for (uint32_t lv = 0; lv < levels; ++lv) {
-        const uint64_t b = level_bound(pixels, params->g, params->r, lv);
-        widest = std::max(widest, b);
-        total += b;
+}  // extern "C"
+
+namespace {
+
+// Render n images (n >= 1) that share one form in one sequence of launches:
+// counters reset, level-0 seeding of every image, then the level kernels or
+// the persistent kernel over one queue. `ims` holds each image's constants.
+ask_status render(ask_ctx *ctx, const Image *ims, uint32_t n, uint32_t form, hipStream_t s,
+                  ask_stats *stats) {
+    uint32_t levels = 0;
+    uint64_t nseeds = 0, bands = 0;
+    std::vector<uint64_t> bound(kMaxLevels, 0);
+    for (uint32_t i = 0; i < n; ++i) {
+        const Image &im = ims[i];
+        const uint32_t lv_i = level_count(im.W, im.H, im.g, im.r, im.B);
+        if (lv_i > (uint32_t)kMaxLevels - 1)
+            return fail(ctx, ASK_EINVAL, "too many levels%s", nullptr);
+        levels = std::max(levels, lv_i);
+        const uint64_t pixels = (uint64_t)im.W * im.H;
+        for (uint32_t lv = 0; lv < lv_i; ++lv)
+            bound[lv] += level_bound(pixels, im.g, im.r, lv);
+        // Leaf bands of the persistent form: every band but a leaf's last
+        // holds at least kLeafTask / 2 pixels.
+        bands += pixels / (kLeafTask / 2);
+        nseeds += (uint64_t)im.g * im.g;
     }
-    const uint32_t form = params->form;
+    if (nseeds > 0x7fffffffull)
+        return fail(ctx, ASK_EINVAL, "too many level-0 regions%s", nullptr);
+    uint64_t widest = 0, total = bands;
+    for (uint32_t lv = 0; lv < levels; ++lv) {
+        widest = std::max(widest, bound[lv]);
+        total += 2 * bound[lv];  // the regions, and at most one last band each
+    }
     const uint64_t need = form == ASK_FORM_PERSISTENT ? total : widest;
     const uint64_t want = std::min<uint64_t>(need, kQueueBudget);
     const bool may_overflow = need > want;
@@ -388,14 +416,59 @@ ask_status ask_dwell_subdiv(ask_ctx *ctx, const ask_window *win, const ask_param
         return st;
 
     SubdivArgs a{};
-    a.table = nullptr;
-    a.single = make_image(win, params, d_out);
-    a.nimg = 1;
-    a.seed_base = nullptr;
+    a.nimg = n;
     a.ctrl = ctx->ctrl;
     a.stats = stats ? ctx->stats : nullptr;
-    const uint32_t nseeds = params->g * params->g;
-    hipError_t e = launch_reset(ctx->ctrl, a.stats, s);
+    hipError_t e = hipSuccess;
+    if (n == 1) {
+        a.single = ims[0];
+    } else {
+        // Image table, then the n + 1 seed offsets, staged through pinned memory.
+        const size_t tbytes = (size_t)n * sizeof(Image);
+        const size_t bytes = tbytes + (size_t)(n + 1) * sizeof(uint32_t);
+        if (ctx->staged) {
+            e = hipEventSynchronize(ctx->staged);  // the previous upload has left staging
+            if (e != hipSuccess)
+                return hip_fail(ctx, e, "hipEventSynchronize");
+        }
+        if (ctx->staging_bytes < bytes) {
+            (void)hipHostFree(ctx->staging);
+            ctx->staging = nullptr;
+            ctx->staging_bytes = 0;
+            if (hipHostMalloc(&ctx->staging, bytes, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(ctx, ASK_ENOMEM, "cannot allocate pinned staging memory%s", nullptr);
+            }
+            ctx->staging_bytes = bytes;
+        }
+        if (ctx->table_bytes < bytes) {
+            e = hipStreamSynchronize(s);
+            if (e == hipSuccess) {
+                (void)hipFree(ctx->table);
+                ctx->table = nullptr;
+                ctx->table_bytes = 0;
+                e = hipMalloc(&ctx->table, bytes);
+            }
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(ctx, ASK_ENOMEM, "cannot allocate the image table%s", nullptr);
+            }
+            ctx->table_bytes = bytes;
+        }
+        memcpy(ctx->staging, ims, tbytes);
+        uint32_t *base = reinterpret_cast<uint32_t *>(static_cast<char *>(ctx->staging) + tbytes);
+        base[0] = 0;
+        for (uint32_t i = 0; i < n; ++i)
+            base[i + 1] = base[i] + ims[i].g * ims[i].g;
+        e = hipMemcpyAsync(ctx->table, ctx->staging, bytes, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipEventRecord(ctx->staged, s);
+        if (e != hipSuccess)
+            return hip_fail(ctx, e, "image table upload");
+        a.table = static_cast<const Image *>(ctx->table);
+        a.seed_base = reinterpret_cast<const uint32_t *>(static_cast<const char *>(ctx->table) + tbytes);
+    }
+    e = launch_reset(ctx->ctrl, a.stats, s);
     if (e != hipSuccess)
         return hip_fail(ctx, e, "reset kernel launch");
 
@@ -411,7 +484,7 @@ ask_status ask_dwell_subdiv(ask_ctx *ctx, const ask_window *win, const ask_param
         a.cap = (uint32_t)std::min<size_t>(ctx->queue_cap, 0xffffffffu - 65536u);
         a.epoch = ctx->epoch;
         a.wait_ticks = (uint64_t)(ctx->wait_limit_s * ctx->clock_hz);
-        e = launch_seed_queue(a, nseeds, s);
+        e = launch_seed_queue(a, (uint32_t)nseeds, s);
         if (e == hipSuccess)
             e = mark(ctx, 0, s);
         if (e == hipSuccess)
@@ -424,7 +497,7 @@ ask_status ask_dwell_subdiv(ask_ctx *ctx, const ask_window *win, const ask_param
         a.cap = (uint32_t)std::min<size_t>(ctx->lvq_cap, 0xffffffffu - 65536u);
         a.epoch = 0;
         a.out = ctx->lvq[0];
-        e = launch_seed_levels(a, nseeds, s);
+        e = launch_seed_levels(a, (uint32_t)nseeds, s);
         if (e == hipSuccess)
             e = mark(ctx, 0, s);
         if (e != hipSuccess)
@@ -435,20 +508,20 @@ ask_status ask_dwell_subdiv(ask_ctx *ctx, const ask_window *win, const ask_param
             a.in = ctx->lvq[lv & 1];
             a.out = ctx->lvq[(lv + 1) & 1];
             if (form == ASK_FORM_LEVELS_READBACK) {
-                uint32_t n = 0;
-                e = hipMemcpyAsync(&n, ctx->ctrl + kCount + lv, sizeof(n), hipMemcpyDeviceToHost, s);
+                uint32_t cnt = 0;
+                e = hipMemcpyAsync(&cnt, ctx->ctrl + kCount + lv, sizeof(cnt), hipMemcpyDeviceToHost,
+                                   s);
                 if (e == hipSuccess)
                     e = hipStreamSynchronize(s);
                 if (e != hipSuccess)
                     return hip_fail(ctx, e, "level count readback");
-                n = std::min<uint32_t>(n, a.cap);
-                if (n == 0)
+                cnt = std::min<uint32_t>(cnt, a.cap);
+                if (cnt == 0)
                     break;
-                e = launch_level_exact(a, n, s);
+                e = launch_level_exact(a, cnt, s);
             } else {
-                const uint64_t bound = level_bound(pixels, params->g, params->r, lv);
-                const uint64_t blocks = std::min<uint64_t>(
-                    resident, (bound + kWavesPerBlock - 1) / kWavesPerBlock);
+                const uint64_t blocks =
+                    std::min<uint64_t>(resident, (bound[lv] + kWavesPerBlock - 1) / kWavesPerBlock);
                 e = launch_level(a, (uint32_t)std::max<uint64_t>(1, blocks), s);
             }
             if (e != hipSuccess)
@@ -461,6 +534,41 @@ ask_status ask_dwell_subdiv(ask_ctx *ctx, const ask_window *win, const ask_param
     if (stats || may_overflow)
         return read_stats(ctx, s, stats);
     return ASK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ask_status ask_dwell_subdiv(ask_ctx *ctx, const ask_window *win, const ask_params *params,
+                            uint32_t *d_out, void *stream, ask_stats *stats) {
+    if (!ctx)
+        return ASK_EINVAL;
+    if (ask_validate(win, params) != ASK_OK || !params || !d_out)
+        return fail(ctx, ASK_EINVAL, "invalid window, parameters or output%s", nullptr);
+    DeviceGuard guard(ctx->device);
+    const Image im = make_image(win, params, d_out);
+    return render(ctx, &im, 1, params->form, (hipStream_t)stream, stats);
+}
+
+ask_status ask_dwell_batch(ask_ctx *ctx, uint32_t n, const ask_window *wins,
+                           const ask_params *params, uint32_t nparams, uint32_t *const *d_outs,
+                           void *stream, ask_stats *stats) {
+    if (!ctx)
+        return ASK_EINVAL;
+    if (n == 0 || !wins || !params || !d_outs || (nparams != 1 && nparams != n))
+        return fail(ctx, ASK_EINVAL, "invalid batch arguments%s", nullptr);
+    const uint32_t form = params[0].form;
+    std::vector<Image> ims(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        const ask_params *p = &params[nparams == 1 ? 0 : i];
+        if (ask_validate(&wins[i], p) != ASK_OK || !d_outs[i] || p->form != form)
+            return fail(ctx, ASK_EINVAL, "invalid window, parameters or output in the batch%s",
+                        nullptr);
+        ims[i] = make_image(&wins[i], p, d_outs[i]);
+    }
+    DeviceGuard guard(ctx->device);
+    return render(ctx, ims.data(), n, form, (hipStream_t)stream, stats);
 }
 
 ask_status ask_enable_timing(ask_ctx *ctx, int on) {

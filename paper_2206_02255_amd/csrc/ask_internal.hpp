@@ -25,9 +25,16 @@ struct Region {
     uint32_t img;   // index into the image table
     uint32_t xy;    // x | y << 16
     uint32_t wh;    // (w - 1) | (h - 1) << 16
-    uint32_t tag;   // epoch << 8 | level; in the persistent queue the tag is
-                    // stored last, with release order, and marks the entry valid
+    uint32_t tag;   // epoch << 8 | kind << 6 | level; in the persistent queue the
+                    // tag is stored last, with release order, and marks the entry valid
 };
+
+// Entry kinds: a region to scan (border query, then fill, leaf or split), or
+// a band of a leaf whose pixels are all computed.
+enum Kind : uint32_t { kScan = 0, kLeaf = 1 };
+
+// Pixels per queued leaf task (persistent form).
+constexpr uint32_t kLeafTask = 1024;
 
 __host__ __device__ inline uint32_t pack_xy(uint32_t x, uint32_t y) { return x | (y << 16); }
 __host__ __device__ inline uint32_t pack_wh(uint32_t w, uint32_t h) { return (w - 1) | ((h - 1) << 16); }

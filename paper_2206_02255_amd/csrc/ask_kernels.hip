@@ -160,6 +160,134 @@ __global__ __launch_bounds__(kBlock) void exhaustive_kernel(Image im) {
     im.out[(size_t)py * im.W + px] = dwell(cr, ci, im.D);
 }
 
+
+// ---------------------------------------------------------------------------
+// Dwell of a stream of pixels with lane refill (border and leaf work).
+//
+// Border and leaf pixels lie on the set boundary, where neighbouring dwells
+// differ by orders of magnitude, so a wave that gives each lane one pixel
+// waits for its slowest pixel with most lanes idle. Here every lane iterates
+// its own pixel, and at each round boundary (kRoundGroups groups of kGroup
+// iterations) every lane whose pixel has finished takes the next pixel of
+// the stream.
+//
+// Escape test per group, without a replay: the group keeps the squares
+// zr^2, zi^2 of every iterate (they are computed anyway) and tests |z|^2 only
+// after its last iteration. When |c|^2 <= 3.99 an orbit that once had
+// |z|^2 > 4 grows at every later step (see dwell()), so a passing test
+// proves no escape inside the group, and a failing one is resolved by
+// looking for the first saved |z|^2 > 4. Lanes with |c|^2 > 3.99 (or NaN)
+// look at every saved |z|^2 of every group, which needs no argument.
+// Iterations past D are harmless: an escape after D, or none by D, give D.
+//
+// pixel_of(i, px, py) names pixel i of the stream (false: no pixel there);
+// done(px, py, dwell) is called by the lane that finished a pixel.
+//
+// Border streams (kBorder) also decide uniformity, and stop as soon as the
+// border is known to be mixed: once some pixel has finished with dwell v,
+// the border is mixed if another pixel finishes with a different dwell, or
+// if a pixel still running has already done v iterations (its dwell is
+// larger than v). The decision is the same as after the whole border; only
+// the remaining iterations are saved. The return value is then false; for a
+// border whose every pixel finished with one value it is true and v holds
+// that value. `partial` receives, per lane, the iterations of a pixel left
+// unfinished by an early stop (work done, for the counters).
+// ---------------------------------------------------------------------------
+constexpr uint32_t kGroup = 8;
+constexpr uint32_t kRoundGroups = 4;
+
+// An empty asm statement that claims to change x: the sums that use x after
+// it cannot be hoisted out of the (rare) branch that holds it.
+__device__ __forceinline__ void pin(double &x) { asm volatile("" : "+v"(x)); }
+
+template <bool kBorder, class PixelOf, class Done>
+__device__ __forceinline__ bool dwell_stream(const Image &im, uint32_t n, PixelOf pixel_of,
+                                             Done done, uint32_t &v, uint32_t &partial) {
+    const uint32_t D = im.D;
+    uint32_t next = 0;  // first stream index no lane has taken yet (uniform)
+    bool have = false, special = false, vset = false;
+    uint32_t px = 0, py = 0, kbase = 0;
+    double cr = 0.0, ci = 0.0, zr = 0.0, zi = 0.0, zr2 = 0.0, zi2 = 0.0;
+    partial = 0;
+    for (;;) {
+        const unsigned long long idle = __ballot(!have);
+        if (idle && next < n) {
+            if (!have) {
+                const uint32_t j = next + lane_rank(idle);
+                if (j < n && pixel_of(j, px, py)) {
+                    have = true;
+                    pixel_c(im, px, py, cr, ci);
+                    special = !(cr * cr + ci * ci <= 3.99);
+                    zr = zi = zr2 = zi2 = 0.0;
+                    kbase = 0;
+                }
+            }
+            next = min(n, next + (uint32_t)__popcll(idle));
+        }
+        if (__ballot(have) == 0)
+            break;
+        uint32_t dw = 0;
+        bool fin = false;
+        if (have) {
+            for (uint32_t gi = 0; gi < kRoundGroups; ++gi) {
+                double sr[kGroup], si[kGroup];
+#pragma unroll
+                for (uint32_t u = 0; u < kGroup; ++u) {
+                    const double zri = zr * zi;
+                    zr = (zr2 - zi2) + cr;
+                    zi = (zri + zri) + ci;
+                    zr2 = zr * zr;
+                    zi2 = zi * zi;
+                    sr[u] = zr2;
+                    si[u] = zi2;
+                }
+                bool esc = !(zr2 + zi2 <= 4.0);
+                if (__builtin_expect(special && !esc, 0)) {
+#pragma unroll
+                    for (uint32_t u = 0; u < kGroup - 1; ++u) {
+                        pin(sr[u]);
+                        esc = esc || (sr[u] + si[u] > 4.0);
+                    }
+                }
+                if (__builtin_expect(esc, 0)) {
+                    uint32_t first = kGroup - 1;
+#pragma unroll
+                    for (int u = kGroup - 2; u >= 0; --u) {
+                        pin(sr[u]);
+                        if (sr[u] + si[u] > 4.0)
+                            first = (uint32_t)u;
+                    }
+                    dw = kbase + first + 1;
+                    fin = true;
+                    break;
+                }
+                kbase += kGroup;
+                if (kbase >= D) {
+                    dw = D;
+                    fin = true;
+                    break;
+                }
+            }
+            if (fin) {
+                dw = dw > D ? D : dw;
+                done(px, py, dw);
+                have = false;
+            }
+        }
+        if (kBorder) {
+            if (!vset && __ballot(fin)) {
+                v = uniform(wave_min(fin ? dw : 0xffffffffu));
+                vset = true;
+            }
+            if (vset && __ballot((fin && dw != v) || (have && kbase >= v))) {
+                partial = have ? kbase : 0u;
+                return false;
+            }
+        }
+    }
+    return true;
+}
+
 // ---------------------------------------------------------------------------
 // Subdivision: one wave owns one region (the single-block-per-region scheme
 // of Sec. 4.3.1 with a wave64 as the block).
@@ -217,31 +345,25 @@ __device__ void fill_region(uint32_t *out, uint32_t W, uint32_t x, uint32_t y, u
     }
 }
 
-// Last-level work L: the dwell of every pixel of the region.
+// Last-level work L: the dwell of every pixel of the region, row-major, as
+// one refilled stream.
 __device__ unsigned long long leaf_region(const Image &im, uint32_t x, uint32_t y, uint32_t w,
-                                          uint32_t h, uint32_t lane) {
+                                          uint32_t h) {
     unsigned long long it = 0;
-    if (w >= kWave) {
-        for (uint32_t row = 0; row < h; ++row)
-            for (uint32_t c = lane; c < w; c += kWave) {
-                double cr, ci;
-                pixel_c(im, x + c, y + row, cr, ci);
-                const uint32_t d = dwell(cr, ci, im.D);
-                im.out[(size_t)(y + row) * im.W + x + c] = d;
-                it += d;
-            }
-    } else {
-        const uint32_t per = kWave / w;
-        const uint32_t lr = lane / w, lc = lane - lr * w;
-        if (lr < per)
-            for (uint32_t row = lr; row < h; row += per) {
-                double cr, ci;
-                pixel_c(im, x + lc, y + row, cr, ci);
-                const uint32_t d = dwell(cr, ci, im.D);
-                im.out[(size_t)(y + row) * im.W + x + lc] = d;
-                it += d;
-            }
-    }
+    uint32_t v, partial;
+    dwell_stream<false>(
+        im, w * h,
+        [&](uint32_t i, uint32_t &px, uint32_t &py) {
+            const uint32_t row = i / w;
+            px = x + (i - row * w);
+            py = y + row;
+            return true;
+        },
+        [&](uint32_t px, uint32_t py, uint32_t d) {
+            im.out[(size_t)py * im.W + px] = d;
+            it += d;
+        },
+        v, partial);
     return it;
 }
 
@@ -249,26 +371,19 @@ __device__ __forceinline__ Image image_of(const SubdivArgs &a, uint32_t img) {
     return a.table ? a.table[img] : a.single;
 }
 
-// S: append the non-empty pieces of the r x r floor partition of the region
-// to the next level (per-level form) or to the queue (persistent form), with
-// one atomic add per wave and per 64 children (Sec. 5.3.1).
-template <bool kQueue>
-__device__ void split_region(const SubdivArgs &a, uint32_t img, uint32_t x, uint32_t y,
-                             uint32_t w, uint32_t h, uint32_t r, uint32_t level, uint32_t lane) {
-    const uint32_t nchild = r * r;
-    const uint32_t tag = (a.epoch << 8) | (level + 1);
-    for (uint32_t base = 0; base < nchild; base += kWave) {
+// Append `count` rectangles (rect_of(j, x0, y0, x1, y1) -> false for an
+// empty one) to the next level (per-level form) or to the queue (persistent
+// form) as entries of the given kind, with one atomic add per wave and per
+// 64 entries: a ballot of the non-empty rectangles and their rank give every
+// entry its slot (Sec. 5.3.1, compact insertion).
+template <bool kQueue, class RectOf>
+__device__ void emit_rects(const SubdivArgs &a, uint32_t img, uint32_t count, uint32_t kind,
+                           uint32_t level, uint32_t lane, RectOf rect_of) {
+    const uint32_t tag = (a.epoch << 8) | (kind << 6) | (level + 1);
+    for (uint32_t base = 0; base < count; base += kWave) {
         const uint32_t j = base + lane;
         uint32_t cx0 = 0, cx1 = 0, cy0 = 0, cy1 = 0;
-        bool ok = false;
-        if (j < nchild) {
-            const uint32_t jx = j % r, jy = j / r;
-            cx0 = x + (uint32_t)(((uint64_t)jx * w) / r);
-            cx1 = x + (uint32_t)(((uint64_t)(jx + 1) * w) / r);
-            cy0 = y + (uint32_t)(((uint64_t)jy * h) / r);
-            cy1 = y + (uint32_t)(((uint64_t)(jy + 1) * h) / r);
-            ok = cx1 > cx0 && cy1 > cy0;
-        }
+        const bool ok = j < count && rect_of(j, cx0, cy0, cx1, cy1);
         const unsigned long long mask = __ballot(ok);
         const uint32_t n = (uint32_t)__popcll(mask);
         if (n == 0)
@@ -297,52 +412,97 @@ __device__ void split_region(const SubdivArgs &a, uint32_t img, uint32_t x, uint
     }
 }
 
+// S: the non-empty pieces of the r x r floor partition of the region become
+// regions of the next level.
+template <bool kQueue>
+__device__ void split_region(const SubdivArgs &a, uint32_t img, uint32_t x, uint32_t y,
+                             uint32_t w, uint32_t h, uint32_t r, uint32_t level, uint32_t lane) {
+    emit_rects<kQueue>(a, img, r * r, kScan, level, lane,
+                       [&](uint32_t j, uint32_t &x0, uint32_t &y0, uint32_t &x1, uint32_t &y1) {
+                           const uint32_t jx = j % r, jy = j / r;
+                           x0 = x + (uint32_t)(((uint64_t)jx * w) / r);
+                           x1 = x + (uint32_t)(((uint64_t)(jx + 1) * w) / r);
+                           y0 = y + (uint32_t)(((uint64_t)jy * h) / r);
+                           y1 = y + (uint32_t)(((uint64_t)(jy + 1) * h) / r);
+                           return x1 > x0 && y1 > y0;
+                       });
+}
+
+// Persistent form: the per-pixel work of a leaf becomes row bands of about
+// kLeafTask pixels, queued as leaf tasks that any wave can take, so that no
+// wave holds a whole leaf while the others idle.
+template <bool kQueue>
+__device__ void queue_leaf_bands(const SubdivArgs &a, uint32_t img, uint32_t x, uint32_t y,
+                                 uint32_t w, uint32_t h, uint32_t level, uint32_t lane) {
+    const uint32_t hb = max(1u, kLeafTask / w);
+    const uint32_t nb = (h + hb - 1) / hb;
+    emit_rects<kQueue>(a, img, nb, kLeaf, level - 1, lane,
+                       [&](uint32_t j, uint32_t &x0, uint32_t &y0, uint32_t &x1, uint32_t &y1) {
+                           x0 = x;
+                           x1 = x + w;
+                           y0 = y + j * hb;
+                           y1 = min(y + h, y0 + hb);
+                           return true;
+                       });
+}
+
 // One region, by one wave: border query Q, then fill T, leaf L or split S
 // (Sec. 4.2.1).
 template <bool kQueue>
 __device__ void process_region(const SubdivArgs &a, const Region &R, uint32_t lane) {
     const uint32_t img = uniform(R.img), xy = uniform(R.xy), wh = uniform(R.wh);
-    const uint32_t level = uniform(R.tag) & 0xffu;
+    const uint32_t tag = uniform(R.tag);
+    const uint32_t level = tag & 0x3fu, kind = (tag >> 6) & 0x3u;
     const Image im = image_of(a, img);
     const uint32_t x = xy & 0xffffu, y = xy >> 16;
     const uint32_t w = (wh & 0xffffu) + 1, h = (wh >> 16) + 1;
-
-    // Q: dwell of every ring pixel, reduced to min and max over the wave.
-    const uint32_t nring = ring_size(w, h);
-    uint32_t vmin = 0xffffffffu, vmax = 0;
-    unsigned long long it = 0;
-    for (uint32_t i = lane; i < nring; i += kWave) {
-        uint32_t px, py;
-        ring_pixel(x, y, w, h, i, px, py);
-        double cr, ci;
-        pixel_c(im, px, py, cr, ci);
-        const uint32_t d = dwell(cr, ci, im.D);
-        vmin = min(vmin, d);
-        vmax = max(vmax, d);
-        it += d;
-    }
-    vmin = uniform(wave_min(vmin));
-    vmax = uniform(wave_max(vmax));
     DevStats *st = a.stats;
+    if (kind == kLeaf) {  // a band of a leaf decided earlier: every pixel
+        unsigned long long li = leaf_region(im, x, y, w, h);
+        if (st)
+            wave_add64(&st->iters_leaf, wave_sum(li));
+        return;
+    }
+
+    // Q: the ring's dwells, in a spread order (the first 64 pixels are spaced
+    // evenly around the ring, the next 64 follow them, ...), until the ring
+    // is known to be mixed or has been computed whole.
+    const uint32_t nring = ring_size(w, h);
+    const uint32_t q = (nring + kWave - 1) / kWave;
+    unsigned long long it = 0;
+    uint32_t v = 0, partial = 0;
+    const bool uniform_ring = dwell_stream<true>(
+        im, q * kWave,
+        [&](uint32_t j, uint32_t &px, uint32_t &py) {
+            const uint32_t t = (j % kWave) * q + j / kWave;
+            if (t >= nring)
+                return false;
+            ring_pixel(x, y, w, h, t, px, py);
+            return true;
+        },
+        [&](uint32_t, uint32_t, uint32_t d) { it += d; }, v, partial);
     if (st) {
-        it = wave_sum(it);
+        it = wave_sum(it + partial);
         wave_add64(&st->regions[level], 1ull);
         wave_add64(&st->iters_ring, it);
         wave_max(&st->levels, level + 1);
     }
-    if (vmin == vmax) {
-        fill_region(im.out, im.W, x, y, w, h, vmin, lane);
+    if (uniform_ring) {
+        fill_region(im.out, im.W, x, y, w, h, v, lane);
         if (st)
             wave_add64(&st->fills[level], 1ull);
         return;
     }
     if (w <= im.B && h <= im.B) {
-        unsigned long long li = leaf_region(im, x, y, w, h, lane);
-        if (st) {
-            li = wave_sum(li);
+        if (st)
             wave_add64(&st->leaves[level], 1ull);
-            wave_add64(&st->iters_leaf, li);
+        if (kQueue && w * h > kLeafTask) {
+            queue_leaf_bands<kQueue>(a, img, x, y, w, h, level, lane);
+            return;
         }
+        unsigned long long li = leaf_region(im, x, y, w, h);
+        if (st)
+            wave_add64(&st->iters_leaf, wave_sum(li));
         return;
     }
     if (level + 1 >= kMaxLevels) {  // unreachable for valid sizes; never write past the tables

@@ -58,7 +58,10 @@ def assert_same_stats(st, ref_st):
     assert st["levels"] == n
     for k in ("regions", "fills", "splits", "leaves"):
         assert st[k][:n] == ref_st[k][:n], k
-    assert st["iters_ring"] == ref_st["iters_ring"]
+    # A ring scan stops once the ring is known to be mixed, so the GPU computes
+    # at most the oracle's ring iterations and at least those of the rings of
+    # filled regions, which must be computed whole; leaves are computed whole.
+    assert ref_st["iters_ring_filled"] <= st["iters_ring"] <= ref_st["iters_ring"]
     assert st["iters_leaf"] == ref_st["iters_leaf"]
     assert st["overflow"] == 0
 

@@ -43,7 +43,7 @@ def check_subdivision(E, S, recs, st, g, r, B):
              for (xa, xb) in floor_parts(0, W, g)}
     assert by_level[0] == want0
     cover = np.zeros_like(E, dtype=np.int32)
-    iters_ring = iters_leaf = ring_new = leaf_inner = 0
+    iters_ring = iters_leaf = ring_new = leaf_inner = ring_filled = 0
     kids_expected = {}
     for rec in recs:
         x, y, w, h, lv, kind, v = (int(rec[k]) for k in ("x", "y", "w", "h", "level", "kind", "value"))
@@ -51,6 +51,7 @@ def check_subdivision(E, S, recs, st, g, r, B):
         iters_ring += int(ring.astype(np.int64).sum())
         uniform = bool((ring == ring[0]).all())
         if kind == FILL:
+            ring_filled += int(ring.astype(np.int64).sum())
             assert uniform and v == ring[0]
             assert (S[y:y + h, x:x + w] == v).all()
             cover[y:y + h, x:x + w] += 1
@@ -92,6 +93,7 @@ def check_subdivision(E, S, recs, st, g, r, B):
     # statistics agree with the records
     assert st["iters_ring"] == iters_ring and st["iters_leaf"] == iters_leaf
     assert st["iters_ring_new"] == ring_new and st["iters_leaf_inner"] == leaf_inner
+    assert st["iters_ring_filled"] == ring_filled
     for lv in range(st["levels"]):
         assert st["regions"][lv] == len(by_level[lv])
         recs_lv = recs[recs["level"] == lv]
