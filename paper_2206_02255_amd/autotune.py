@@ -1,0 +1,183 @@
+"""Autotuner for the subdivision parameters (g, r, B), beside the cost model.
+
+The paper searches {g, r, B} by measurement (Sec. 6.2) and predicts the best
+values with its cost model (Sec. 4.3). This module does both for a window on
+the GPU:
+
+* ``sweep`` renders the window once per candidate (the kernel's own device
+  time, best of ``reps``) and records the counters of the render;
+* ``fit_model`` fits the two unknowns of the time model to the measurements:
+  the split cost lambda (S = lambda A) and the seconds per model time unit,
+  with P the measured split probability and q = CUs, c = 64 lanes;
+* ``tune`` returns the measured optimum and the model optimum, and caches the
+  measured choice in a JSON file keyed by the workload class.
+
+Run ``python -m paper_2206_02255_amd.autotune --size 16384 --dwell 2048`` for
+the sweep of the paper's window.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+
+import numpy as np
+
+from . import ask, costmodel
+
+PAPER_OPTIMA = {
+    "abstract (cost model)": "g in [2, 16], r in {2, 4}, B ~ 32",
+    "conclusions (cost model)": "g in [2, 64], r ~ 2, B ~ 32",
+    "experiments, ASK-SBR": "{g, r, B} = {32 or 64, 4, 16}",
+    "experiments, ASK-MBR": "{g, r, B} = {32 or 64, 2, 32}",
+}
+
+
+def default_grid(n):
+    """(g, r, B) candidates for an n-pixel side: g and B powers of two,
+    r in {2, 4, 8}, keeping at least one split level."""
+    out = []
+    for g in (2, 4, 8, 16, 32, 64, 128, 256):
+        for r in (2, 4, 8):
+            for B in (16, 32, 64, 128):
+                if g <= n and n // g > B:
+                    out.append((g, r, B))
+    return out
+
+
+def sweep(ctx, win, grid, form="persistent", reps=3, out=None):
+    """Measure every (g, r, B) of ``grid`` on window ``win`` (an ask_window).
+    Returns one dict per candidate: g, r, B, ms (kernel device time, best of
+    reps), iterations, P (measured split probability) and the counters."""
+    import torch
+    stream = torch.cuda.current_stream().cuda_stream
+    if out is None:
+        out = torch.empty(win.W * win.H, dtype=torch.int32, device="cuda")
+    ask.ask_enable_timing(ctx, True)
+    rows = []
+    try:
+        for g, r, B in grid:
+            prm = ask.params(g, r, B, form)
+            st = ask.ask_dwell_subdiv(ctx, win, prm, out.data_ptr(), stream, want_stats=True)
+            best = math.inf
+            for _ in range(reps):
+                ask.ask_dwell_subdiv(ctx, win, prm, out.data_ptr(), stream)
+                best = min(best, ask.ask_last_kernel_ms(ctx))
+            rows.append({"g": g, "r": r, "B": B, "ms": best,
+                         "iterations": st["iters_ring"] + st["iters_leaf"],
+                         "P": costmodel.split_probability(st),
+                         "regions": sum(st["regions"]), "levels": st["levels"]})
+    finally:
+        ask.ask_enable_timing(ctx, False)
+        ask.ask_synchronize(ctx, stream)
+    return rows
+
+
+def fit_model(rows, n, A, q, c=64, lambdas=None):
+    """Fit lambda and the seconds per model unit so that kappa * T_SBR(g, r, B)
+    matches the measured times in the least-squares sense of log time. P is
+    the median of the measured split probabilities (the SSD assumption of one
+    P for the problem). Returns (lambda, kappa, P, relative rms error)."""
+    if lambdas is None:
+        lambdas = [0.0] + list(np.logspace(-1, 5, 25))
+    P = float(np.median([row["P"] for row in rows]))
+    g = np.array([row["g"] for row in rows], dtype=np.float64)
+    r = np.array([row["r"] for row in rows], dtype=np.float64)
+    B = np.array([row["B"] for row in rows], dtype=np.float64)
+    t = np.log(np.array([row["ms"] for row in rows]))
+    best = None
+    for lam in lambdas:
+        m = np.log(costmodel.time_sbr(n, g, r, B, A, P, lam, q, c))
+        k = float(np.mean(t - m))
+        err = float(np.sqrt(np.mean((t - m - k) ** 2)))
+        if best is None or err < best[3]:
+            best = (float(lam), math.exp(k), P, err)
+    return best
+
+
+def model_optimum(grid, n, A, P, lam, q, c=64, scheme="sbr"):
+    """The (g, r, B) of ``grid`` that the time model ranks fastest."""
+    g, r, B = (np.array([p[i] for p in grid], dtype=np.float64) for i in range(3))
+    f = costmodel.time_sbr if scheme == "sbr" else costmodel.time_mbr
+    t = f(n, g, r, B, A, P, lam, q, c)
+    i = int(np.argmin(t))
+    return tuple(int(v) for v in grid[i]), float(t[i])
+
+
+def cache_path():
+    return os.environ.get("ASK_TUNE_CACHE", os.path.join(
+        os.path.expanduser("~"), ".cache", "paper_2206_02255_amd", "tune.json"))
+
+
+def workload_key(win, form):
+    width = max(win.x1 - win.x0, win.y1 - win.y0)
+    return "%dx%d-D%d-w1e%d-%s" % (win.W, win.H, win.D, int(math.floor(math.log10(width))), form)
+
+
+def tune(ctx, win, grid=None, form="persistent", reps=3, q=256, use_cache=True):
+    """Measured optimum (g, r, B) for window ``win``, from the cache when it
+    holds this workload class, else from a sweep (then cached). Returns a
+    dict with the measured optimum, the model optimum and the sweep rows."""
+    key = workload_key(win, form)
+    path = cache_path()
+    cache = {}
+    if use_cache and os.path.exists(path):
+        with open(path) as f:
+            cache = json.load(f)
+        if key in cache:
+            return cache[key]
+    grid = grid or default_grid(min(win.W, win.H))
+    rows = sweep(ctx, win, grid, form, reps)
+    n = min(win.W, win.H)
+    lam, kappa, P, err = fit_model(rows, n, float(win.D), q)
+    best = min(rows, key=lambda row: row["ms"])
+    (mg, mr, mB), _ = model_optimum(grid, n, float(win.D), P, lam, q)
+    measured_at_model = next(row["ms"] for row in rows if (row["g"], row["r"], row["B"]) == (mg, mr, mB))
+    result = {"key": key, "form": form,
+              "measured_optimum": {"g": best["g"], "r": best["r"], "B": best["B"], "ms": best["ms"]},
+              "model_optimum": {"g": mg, "r": mr, "B": mB, "ms_measured": measured_at_model},
+              "model_fit": {"lambda": lam, "seconds_per_unit": kappa * 1e-3, "P": P,
+                            "log_rms_error": err, "q": q, "c": 64},
+              "rows": rows}
+    if use_cache:
+        cache[key] = result
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        with open(path, "w") as f:
+            json.dump(cache, f, indent=1)
+    return result
+
+
+def main(argv=None):
+    import torch
+    ap = argparse.ArgumentParser(description="(g, r, B) sweep on the paper's window")
+    ap.add_argument("--size", type=int, default=16384)
+    ap.add_argument("--dwell", type=int, default=2048)
+    ap.add_argument("--form", default="persistent", choices=["levels", "persistent"])
+    ap.add_argument("--grid", default="paper", choices=["paper", "wide"])
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--json", default=None, help="write the result here")
+    args = ap.parse_args(argv)
+    from workloads import LARGE_SWEEP, paper_window
+    w = paper_window(args.size, args.dwell)
+    grid = ([(p.g, p.r, p.B) for p in LARGE_SWEEP] if args.grid == "paper"
+            else default_grid(args.size))
+    ctx = ask.ask_create(0)
+    try:
+        props = torch.cuda.get_device_properties(0)
+        res = tune(ctx, ask.window(w), grid, args.form, args.reps,
+                   q=props.multi_processor_count, use_cache=False)
+    finally:
+        ask.ask_destroy(ctx)
+    res["paper_optima"] = PAPER_OPTIMA
+    for row in sorted(res["rows"], key=lambda row: row["ms"])[:10]:
+        print("g=%3d r=%d B=%3d  %8.3f ms  P=%.3f  iterations=%d" %
+              (row["g"], row["r"], row["B"], row["ms"], row["P"], row["iterations"]), flush=True)
+    print(json.dumps({k: res[k] for k in ("measured_optimum", "model_optimum", "model_fit")}))
+    if args.json:
+        with open(args.json, "w") as f:
+            json.dump(res, f, indent=1)
+
+
+if __name__ == "__main__":
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    main()
