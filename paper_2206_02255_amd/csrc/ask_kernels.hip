@@ -167,18 +167,16 @@ __global__ __launch_bounds__(kBlock) void exhaustive_kernel(Image im) {
 // Border and leaf pixels lie on the set boundary, where neighbouring dwells
 // differ by orders of magnitude, so a wave that gives each lane one pixel
 // waits for its slowest pixel with most lanes idle. Here every lane iterates
-// its own pixel, and at each round boundary (kRoundGroups groups of kGroup
-// iterations) every lane whose pixel has finished takes the next pixel of
-// the stream.
+// its own pixel, and at each round boundary (kRoundBlocks stretches of
+// kStride iterations) every lane whose pixel has finished takes the next
+// pixel of the stream.
 //
-// Escape test per group, without a replay: the group keeps the squares
-// zr^2, zi^2 of every iterate (they are computed anyway) and tests |z|^2 only
-// after its last iteration. When |c|^2 <= 3.99 an orbit that once had
-// |z|^2 > 4 grows at every later step (see dwell()), so a passing test
-// proves no escape inside the group, and a failing one is resolved by
-// looking for the first saved |z|^2 > 4. Lanes with |c|^2 > 3.99 (or NaN)
-// look at every saved |z|^2 of every group, which needs no argument.
-// Iterations past D are harmless: an escape after D, or none by D, give D.
+// Each stretch is the fast loop of dwell(): kStride iterations without a
+// test, then !(|z|^2 <= 4); a failing test restarts the stretch from its
+// saved start with a test after every iteration. Lanes with |c|^2 > 3.99 (or
+// NaN) test after every iteration throughout. Iterations past D are
+// harmless: an escape after D, or none by D, both give D, so D is checked
+// once per round.
 //
 // pixel_of(i, px, py) names pixel i of the stream (false: no pixel there);
 // done(px, py, dwell) is called by the lane that finished a pixel.
@@ -193,12 +191,7 @@ __global__ __launch_bounds__(kBlock) void exhaustive_kernel(Image im) {
 // that value. `partial` receives, per lane, the iterations of a pixel left
 // unfinished by an early stop (work done, for the counters).
 // ---------------------------------------------------------------------------
-constexpr uint32_t kGroup = 8;
-constexpr uint32_t kRoundGroups = 4;
-
-// An empty asm statement that claims to change x: the sums that use x after
-// it cannot be hoisted out of the (rare) branch that holds it.
-__device__ __forceinline__ void pin(double &x) { asm volatile("" : "+v"(x)); }
+constexpr uint32_t kRoundBlocks = 2;
 
 template <bool kBorder, class PixelOf, class Done>
 __device__ __forceinline__ bool dwell_stream(const Image &im, uint32_t n, PixelOf pixel_of,
@@ -229,44 +222,48 @@ __device__ __forceinline__ bool dwell_stream(const Image &im, uint32_t n, PixelO
         uint32_t dw = 0;
         bool fin = false;
         if (have) {
-            for (uint32_t gi = 0; gi < kRoundGroups; ++gi) {
-                double sr[kGroup], si[kGroup];
+            for (uint32_t bi = 0; bi < kRoundBlocks && !fin; ++bi) {
+                if (__builtin_expect(!special, 1)) {
+                    const double szr = zr, szi = zi, szr2 = zr2, szi2 = zi2;
 #pragma unroll
-                for (uint32_t u = 0; u < kGroup; ++u) {
-                    const double zri = zr * zi;
-                    zr = (zr2 - zi2) + cr;
-                    zi = (zri + zri) + ci;
-                    zr2 = zr * zr;
-                    zi2 = zi * zi;
-                    sr[u] = zr2;
-                    si[u] = zi2;
-                }
-                bool esc = !(zr2 + zi2 <= 4.0);
-                if (__builtin_expect(special && !esc, 0)) {
-#pragma unroll
-                    for (uint32_t u = 0; u < kGroup - 1; ++u) {
-                        pin(sr[u]);
-                        esc = esc || (sr[u] + si[u] > 4.0);
+                    for (uint32_t u = 0; u < kStride; ++u) {
+                        const double zri = zr * zi;
+                        zr = (zr2 - zi2) + cr;
+                        zi = (zri + zri) + ci;
+                        zr2 = zr * zr;
+                        zi2 = zi * zi;
                     }
-                }
-                if (__builtin_expect(esc, 0)) {
-                    uint32_t first = kGroup - 1;
-#pragma unroll
-                    for (int u = kGroup - 2; u >= 0; --u) {
-                        pin(sr[u]);
-                        if (sr[u] + si[u] > 4.0)
-                            first = (uint32_t)u;
+                    if (!(zr2 + zi2 <= 4.0)) {
+                        // escaped inside the stretch: find the first k again
+                        zr = szr;
+                        zi = szi;
+                        zr2 = szr2;
+                        zi2 = szi2;
+                        dw = dwell_from(cr, ci, D, kbase, zr, zi, zr2, zi2);
+                        fin = true;
+                    } else {
+                        kbase += kStride;
                     }
-                    dw = kbase + first + 1;
-                    fin = true;
-                    break;
+                } else {
+                    for (uint32_t u = 0; u < kStride; ++u) {
+                        const double zri = zr * zi;
+                        zr = (zr2 - zi2) + cr;
+                        zi = (zri + zri) + ci;
+                        zr2 = zr * zr;
+                        zi2 = zi * zi;
+                        if (zr2 + zi2 > 4.0) {
+                            dw = kbase + u + 1;
+                            fin = true;
+                            break;
+                        }
+                    }
+                    if (!fin)
+                        kbase += kStride;
                 }
-                kbase += kGroup;
-                if (kbase >= D) {
-                    dw = D;
-                    fin = true;
-                    break;
-                }
+            }
+            if (!fin && kbase >= D) {
+                dw = D;
+                fin = true;
             }
             if (fin) {
                 dw = dw > D ? D : dw;
