@@ -7,10 +7,14 @@ without sharing any of the method.
 
 Workloads follow the paper's experiment (Sec. 6.1): the Mandelbrot set over
 the window with corners (-1.5, -1) and (0.5, 1), square images, dwell limit
-512, and the subdivision parameter grid {g, r, B} (Sec. 6.2).
+512, and the subdivision parameter grid {g, r, B} (Sec. 6.2). The deep-zoom,
+batched and serving workloads centre their windows on points of a stored
+pool of boundary points (inputs/boundary_pool.txt, written once by
+oracle/make_boundary_pool.py); this module only reads it.
 """
 from dataclasses import dataclass
 import math
+import os
 
 import numpy as np
 
@@ -91,3 +95,77 @@ def random_params(seed, window, count):
         B = int(rng.integers(1, 64))
         out.append(Params(g, r, B))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Boundary-centred workloads.
+# ---------------------------------------------------------------------------
+POOL_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "inputs",
+                         "boundary_pool.txt")
+BATCH_DWELLS = (256, 1024, 4096, 8192)
+
+
+def boundary_pool():
+    """The stored boundary points, as (x, y) pairs of floats, in file order."""
+    out = []
+    with open(POOL_PATH) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            a, b = line.split()
+            out.append((float.fromhex(a), float.fromhex(b)))
+    return out
+
+
+def centred(cx, cy, width, W, H, D):
+    """Window of the given width (and the image's aspect) centred on (cx, cy)."""
+    hw = width / 2
+    hh = hw * H / W
+    return Window(cx - hw, cx + hw, cy - hh, cy + hh, W, H, D)
+
+
+def deep_window(seed=3, n=32768, D=8192, width=1e-6):
+    """The deep-zoom single image: a pool point chosen with `seed`, a window
+    of the given width around it, n x n pixels."""
+    pool = boundary_pool()
+    cx, cy = pool[int(np.random.default_rng(seed).integers(len(pool)))]
+    return centred(cx, cy, width, n, n, D)
+
+
+def batch_params(side):
+    """(g, r, B) for a batch or serving image of the given side: level-0
+    regions of about 256 pixels, r = 2, B = 32 (the best setting of the
+    16384 x 16384 sweep, scaled to the image)."""
+    return Params(max(1, min(256, side // 256)), 2, 32)
+
+
+def _draw_image(rng, pool, index=None, side_range=(512, 8192), width_range=(1e-10, 2.0)):
+    side = int(math.floor(math.exp(rng.uniform(math.log(side_range[0]), math.log(side_range[1])))))
+    width = math.exp(rng.uniform(math.log(width_range[0]), math.log(width_range[1])))
+    i = int(rng.integers(len(pool))) if index is None else index
+    D = int(BATCH_DWELLS[int(rng.integers(len(BATCH_DWELLS)))])
+    cx, cy = pool[i]
+    return centred(cx, cy, width, side, side, D)
+
+
+def batch_images(seed=4, count=256, side_range=(512, 8192)):
+    """The batched workload: `count` square images, sides log-uniform in
+    side_range, widths log-uniform in [1e-10, 2], image i centred on pool
+    point i (mod the pool size), maximum dwell uniform in BATCH_DWELLS."""
+    pool = boundary_pool()
+    rng = np.random.default_rng(seed)
+    return [_draw_image(rng, pool, i % len(pool), side_range) for i in range(count)]
+
+
+def serving_requests(seed=5, rate=200.0, seconds=60.0, side_range=(512, 8192)):
+    """The serving workload: Poisson arrivals at `rate` per second for
+    `seconds`; each request is (arrival time in s, window) drawn like a batch
+    image, centred on a pool point chosen at random."""
+    pool = boundary_pool()
+    rng = np.random.default_rng(seed)
+    out, t = [], 0.0
+    while True:
+        t += float(rng.exponential(1.0 / rate))
+        if t >= seconds:
+            return out
+        out.append((t, _draw_image(rng, pool, None, side_range)))
