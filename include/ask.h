@@ -82,7 +82,7 @@ typedef enum ask_form {
 /* Subdivision parameters (Sec. 4.2.1, 6.2): an initial g x g grid of
  * regions, r x r splits, stop size B (a region with both sides <= B whose
  * border is not uniform is computed per pixel). Valid: 1 <= g <= min(W, H),
- * 2 <= r <= 8, 1 <= B <= 65536. form: an ask_form. */
+ * 2 <= r <= 1024, 1 <= B <= 65536. form: an ask_form. */
 typedef struct ask_params {
     uint32_t g, r, B;
     uint32_t form;
@@ -186,6 +186,75 @@ ask_status ask_last_kernel_ms(ask_ctx *ctx, float *ms);
  * leaves. This bounds every wait of the kernel, so its grid always drains;
  * a render never legitimately idles a wave for seconds. */
 ask_status ask_set_wait_limit(ask_ctx *ctx, double seconds);
+
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching into one persistent kernel.
+ *
+ * A server owns one long-running kernel on a stream of its own. Requests
+ * (a window, its parameters and a caller-owned output image) are posted
+ * while the kernel runs; an idle wave admits a posted request into a free
+ * slot, writes its level-0 regions into that request's own region queue in
+ * device memory, and from then on every wave of the kernel takes regions of
+ * any admitted request, so requests that arrive while others run overlap
+ * with them on the device. The wave that finishes a request's last region
+ * reports it to the host through pinned host memory. Each image is the one
+ * ask_dwell_subdiv gives for the same window and parameters, bit for bit.
+ *
+ * Admission is by device memory: each request reserves, in the server's
+ * pool, the worst-case size of its region queue and ring records (the
+ * bounds ask_dwell_subdiv sizes its queue by); a request that does not fit,
+ * or finds every slot taken, is refused with ASK_EBUSY and can be posted
+ * again once earlier requests have finished.
+ *
+ * The kernel keeps waves_per_cu waves resident on every CU until
+ * ask_server_destroy; other kernels on the device run beside it in the room
+ * it leaves. One server per context; a server is not thread-safe.
+ * ------------------------------------------------------------------------ */
+typedef struct ask_server ask_server;
+
+typedef struct ask_server_cfg {
+    uint32_t slots;        /* requests admitted at once, 1..64 */
+    uint32_t waves_per_cu; /* resident server waves per CU, a multiple of 4;
+                              0: all but one 4-wave workgroup of the
+                              kernel's occupancy */
+    uint64_t pool_bytes;   /* device memory for the requests' region queues
+                              and ring records (0: 256 MiB) */
+} ask_server_cfg;
+
+/* Start a server on ctx's device. *out receives it, or NULL on error. */
+ask_status ask_server_create(ask_ctx *ctx, const ask_server_cfg *cfg, ask_server **out);
+
+/* Post one request. win and params are checked as for ask_dwell_subdiv
+ * (params->form is ignored). d_out: device memory, W*H uint32, caller-owned,
+ * not to be read or freed until the request has finished. On ASK_OK,
+ * *ticket receives the request's ticket (increasing from 1). ASK_EBUSY: no
+ * free slot or not enough pool memory right now (finished requests are
+ * reaped first, so retrying after a completion can succeed); ASK_ENOMEM:
+ * the request's worst case exceeds the whole pool. */
+ask_status ask_server_submit(ask_server *sv, const ask_window *win,
+                             const ask_params *params, uint32_t *d_out,
+                             uint64_t *ticket);
+
+/* Collect finished requests: up to cap of them, in any order, into
+ * tickets[] with each one's status (ASK_OK; ASK_ETIMEOUT or ASK_EOVERFLOW
+ * for a request whose image is invalid) in status[] (may be NULL); *n gets
+ * the count. A finished request's image is complete in device memory and
+ * visible to later work on any stream. Does not wait. */
+ask_status ask_server_reap(ask_server *sv, uint64_t *tickets, int32_t *status,
+                           uint32_t cap, uint32_t *n);
+
+/* *done = 1 when request `ticket` has finished (reaping it if needed), else
+ * 0. Returns the request's status once finished; ASK_EINVAL for a ticket
+ * never issued. Does not wait. */
+ask_status ask_server_poll(ask_server *sv, uint64_t ticket, int *done);
+
+/* Requests posted and not yet reaped. */
+ask_status ask_server_in_flight(const ask_server *sv, uint32_t *n);
+
+/* Wait (up to the context's wait limit) for the requests in flight, stop
+ * the kernel and release the server. NULL is accepted. ASK_ETIMEOUT if the
+ * requests did not finish in time (the kernel is still stopped). */
+ask_status ask_server_destroy(ask_server *sv);
 
 #ifdef __cplusplus
 }

@@ -4,10 +4,16 @@
 #include "ask.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <iterator>
+#include <map>
 #include <new>
+#include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "ask_internal.hpp"
@@ -25,6 +31,8 @@ struct ask_ctx {
     size_t lvq_cap = 0;                   // entries per table
     Region *queue = nullptr;              // persistent queue
     size_t queue_cap = 0;
+    RingRec *recs = nullptr;              // persistent form: segmented ring records
+    size_t rec_cap = 0;
     uint32_t epoch = 0;                   // 24-bit launch counter for queue tags
     double wait_limit_s = 10.0;           // persistent kernel: longest wait of one wave
     double clock_hz = 1e8;                // rate of the device's constant clock
@@ -38,6 +46,11 @@ struct ask_ctx {
     void *staging = nullptr;
     size_t staging_bytes = 0;
     hipEvent_t staged = nullptr;
+    // Completion of the last render or exhaustive image enqueued on this
+    // context (any stream): buffers are reallocated only after it.
+    hipEvent_t last = nullptr;
+    bool last_set = false;
+    ask_server *server = nullptr;  // the context's server, if one runs
     char err[512] = {0};
 };
 
@@ -128,6 +141,49 @@ uint64_t level_bound(uint64_t pixels, uint32_t g, uint32_t r, uint32_t lv) {
     return b >= (double)pixels ? pixels : (uint64_t)b;
 }
 
+// Worst-case work memory of a set of images (persistent form unless noted).
+struct Bounds {
+    std::vector<uint64_t> level = std::vector<uint64_t>(kMaxLevels, 0);  // regions per level
+    uint64_t bands = 0;  // leaf bands
+    uint64_t segs = 0;   // extra ring-segment entries
+    uint64_t recs = 0;   // ring records
+    // Queue entries: bands and segments, and per level the regions and at
+    // most one last (short) band each.
+    uint64_t queue_entries() const {
+        uint64_t t = bands + segs;
+        for (uint64_t v : level)
+            t += 2 * v;
+        return t;
+    }
+};
+
+// Add one image's bounds to b; returns its level count.
+uint32_t add_bounds(const Image &im, Bounds &b) {
+    const uint32_t lv_i = level_count(im.W, im.H, im.g, im.r, im.B);
+    const uint64_t pixels = (uint64_t)im.W * im.H;
+    // Largest piece of each level (sw x sh), for the ring segments: a
+    // segmented ring has more than kSegPx pixels, so at most
+    // pixels / (kSegPx + 1) regions of a level have one, and their extra
+    // segment entries (ceil(ring / kSegPx) - 1 each) number at most
+    // pixels / kSegPx, the rings of a level being disjoint.
+    uint64_t sw = (im.W + im.g - 1) / im.g, sh = (im.H + im.g - 1) / im.g;
+    for (uint32_t lv = 0; lv < lv_i && lv < (uint32_t)kMaxLevels; ++lv) {
+        const uint64_t c = level_bound(pixels, im.g, im.r, lv);
+        b.level[lv] += c;
+        const uint64_t ring = (sw == 1 || sh == 1) ? sw * sh : 2 * (sw + sh) - 4;
+        if (ring > kSegPx) {
+            b.recs += std::min<uint64_t>(c, pixels / (kSegPx + 1));
+            b.segs += std::min<uint64_t>(pixels / kSegPx, c * ((ring + kSegPx - 1) / kSegPx - 1));
+        }
+        sw = (sw + im.r - 1) / im.r;
+        sh = (sh + im.r - 1) / im.r;
+    }
+    // Leaf bands: every band but a leaf's last holds at least kLeafTask / 2
+    // pixels.
+    b.bands += pixels / (kLeafTask / 2);
+    return lv_i;
+}
+
 Image make_image(const ask_window *w, const ask_params *p, uint32_t *out) {
     double m[4];
     mapping(w, m);
@@ -146,27 +202,39 @@ Image make_image(const ask_window *w, const ask_params *p, uint32_t *out) {
     return im;
 }
 
-ask_status grow(ask_ctx *ctx, Region **buf, size_t *cap, size_t need, bool clear) {
+// Wait until the context's last enqueued render has finished.
+hipError_t wait_last(ask_ctx *ctx) {
+    return ctx->last_set ? hipEventSynchronize(ctx->last) : hipSuccess;
+}
+
+hipError_t note_last(ask_ctx *ctx, hipStream_t s) {
+    hipError_t e = hipEventRecord(ctx->last, s);
+    ctx->last_set = e == hipSuccess;
+    return e;
+}
+
+template <class T>
+ask_status grow(ask_ctx *ctx, T **buf, size_t *cap, size_t need, bool clear) {
     if (*cap >= need)
         return ASK_OK;
     const size_t n = std::max<size_t>(need, std::min<size_t>(*cap * 2, kQueueBudget));
     hipError_t e;
     if (*buf) {
-        e = hipDeviceSynchronize();
+        e = wait_last(ctx);
         if (e != hipSuccess)
-            return hip_fail(ctx, e, "hipDeviceSynchronize");
+            return hip_fail(ctx, e, "hipEventSynchronize");
         (void)hipFree(*buf);
         *buf = nullptr;
         *cap = 0;
     }
-    e = hipMalloc((void **)buf, n * sizeof(Region));
+    e = hipMalloc((void **)buf, n * sizeof(T));
     if (e != hipSuccess) {
         *buf = nullptr;
         (void)hipGetLastError();
-        return fail(ctx, ASK_ENOMEM, "cannot allocate the region queue%s", nullptr);
+        return fail(ctx, ASK_ENOMEM, "cannot allocate the region queue or ring records%s", nullptr);
     }
     if (clear) {
-        e = hipMemset(*buf, 0, n * sizeof(Region));
+        e = hipMemset(*buf, 0, n * sizeof(T));
         if (e != hipSuccess)
             return hip_fail(ctx, e, "hipMemset");
     }
@@ -302,6 +370,8 @@ ask_status ask_create(ask_ctx **out, int device) {
     if (e == hipSuccess)
         e = hipEventCreateWithFlags(&ctx->staged, hipEventDisableTiming);
     if (e == hipSuccess)
+        e = hipEventCreateWithFlags(&ctx->last, hipEventDisableTiming);
+    if (e == hipSuccess)
         e = occupancy_level(&ctx->occ_level);
     if (e == hipSuccess)
         e = occupancy_persistent(&ctx->occ_persistent);
@@ -325,6 +395,8 @@ ask_status ask_create(ask_ctx **out, int device) {
 ask_status ask_destroy(ask_ctx *ctx) {
     if (!ctx)
         return ASK_OK;
+    if (ctx->server)
+        (void)ask_server_destroy(ctx->server);
     {
         DeviceGuard guard(ctx->device);
         (void)hipDeviceSynchronize();
@@ -333,12 +405,15 @@ ask_status ask_destroy(ask_ctx *ctx) {
         (void)hipFree(ctx->lvq[0]);
         (void)hipFree(ctx->lvq[1]);
         (void)hipFree(ctx->queue);
+        (void)hipFree(ctx->recs);
         if (ctx->ev[0])
             (void)hipEventDestroy(ctx->ev[0]);
         if (ctx->ev[1])
             (void)hipEventDestroy(ctx->ev[1]);
         if (ctx->staged)
             (void)hipEventDestroy(ctx->staged);
+        if (ctx->last)
+            (void)hipEventDestroy(ctx->last);
         (void)hipFree(ctx->table);
         (void)hipHostFree(ctx->staging);
     }
@@ -359,6 +434,8 @@ ask_status ask_dwell_exhaustive(ask_ctx *ctx, const ask_window *win, uint32_t *d
         e = launch_exhaustive(im, (hipStream_t)stream);
     if (e == hipSuccess)
         e = mark(ctx, 1, (hipStream_t)stream);
+    if (e == hipSuccess)
+        e = note_last(ctx, (hipStream_t)stream);
     if (e != hipSuccess)
         return hip_fail(ctx, e, "exhaustive kernel launch");
     return ASK_OK;
@@ -374,35 +451,32 @@ namespace {
 ask_status render(ask_ctx *ctx, const Image *ims, uint32_t n, uint32_t form, hipStream_t s,
                   ask_stats *stats) {
     uint32_t levels = 0;
-    uint64_t nseeds = 0, bands = 0;
-    std::vector<uint64_t> bound(kMaxLevels, 0);
+    uint64_t nseeds = 0;
+    Bounds b;
     for (uint32_t i = 0; i < n; ++i) {
         const Image &im = ims[i];
-        const uint32_t lv_i = level_count(im.W, im.H, im.g, im.r, im.B);
+        const uint32_t lv_i = add_bounds(im, b);
         if (lv_i > (uint32_t)kMaxLevels - 1)
             return fail(ctx, ASK_EINVAL, "too many levels%s", nullptr);
         levels = std::max(levels, lv_i);
-        const uint64_t pixels = (uint64_t)im.W * im.H;
-        for (uint32_t lv = 0; lv < lv_i; ++lv)
-            bound[lv] += level_bound(pixels, im.g, im.r, lv);
-        // Leaf bands of the persistent form: every band but a leaf's last
-        // holds at least kLeafTask / 2 pixels.
-        bands += pixels / (kLeafTask / 2);
         nseeds += (uint64_t)im.g * im.g;
     }
     if (nseeds > 0x7fffffffull)
         return fail(ctx, ASK_EINVAL, "too many level-0 regions%s", nullptr);
-    uint64_t widest = 0, total = bands;
-    for (uint32_t lv = 0; lv < levels; ++lv) {
+    const std::vector<uint64_t> &bound = b.level;
+    const uint64_t recs = b.recs;
+    uint64_t widest = 0;
+    for (uint32_t lv = 0; lv < levels; ++lv)
         widest = std::max(widest, bound[lv]);
-        total += 2 * bound[lv];  // the regions, and at most one last band each
-    }
+    const uint64_t total = b.queue_entries();
     const uint64_t need = form == ASK_FORM_PERSISTENT ? total : widest;
     const uint64_t want = std::min<uint64_t>(need, kQueueBudget);
-    const bool may_overflow = need > want;
+    const bool may_overflow = need > want || recs > kQueueBudget;
     ask_status st;
     if (form == ASK_FORM_PERSISTENT) {
         st = grow(ctx, &ctx->queue, &ctx->queue_cap, want, true);
+        if (st == ASK_OK && recs > 0)
+            st = grow(ctx, &ctx->recs, &ctx->rec_cap, std::min<uint64_t>(recs, kQueueBudget), false);
     } else {
         size_t cap0 = ctx->lvq_cap;
         st = grow(ctx, &ctx->lvq[0], &cap0, want, false);
@@ -442,7 +516,7 @@ ask_status render(ask_ctx *ctx, const Image *ims, uint32_t n, uint32_t form, hip
             ctx->staging_bytes = bytes;
         }
         if (ctx->table_bytes < bytes) {
-            e = hipStreamSynchronize(s);
+            e = wait_last(ctx);
             if (e == hipSuccess) {
                 (void)hipFree(ctx->table);
                 ctx->table = nullptr;
@@ -482,6 +556,8 @@ ask_status render(ask_ctx *ctx, const Image *ims, uint32_t n, uint32_t form, hip
         }
         a.queue = ctx->queue;
         a.cap = (uint32_t)std::min<size_t>(ctx->queue_cap, 0xffffffffu - 65536u);
+        a.recs = ctx->recs;
+        a.rec_cap = (uint32_t)std::min<size_t>(ctx->rec_cap, 0xffffffffu);
         a.epoch = ctx->epoch;
         a.wait_ticks = (uint64_t)(ctx->wait_limit_s * ctx->clock_hz);
         e = launch_seed_queue(a, (uint32_t)nseeds, s);
@@ -531,6 +607,9 @@ ask_status render(ask_ctx *ctx, const Image *ims, uint32_t n, uint32_t form, hip
         if (e != hipSuccess)
             return hip_fail(ctx, e, "hipEventRecord");
     }
+    e = note_last(ctx, s);
+    if (e != hipSuccess)
+        return hip_fail(ctx, e, "hipEventRecord");
     if (stats || may_overflow)
         return read_stats(ctx, s, stats);
     return ASK_OK;
@@ -605,6 +684,372 @@ ask_status ask_synchronize(ask_ctx *ctx, void *stream) {
         return ASK_EINVAL;
     DeviceGuard guard(ctx->device);
     return take_errors(ctx, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Serving (include/ask.h): slots, pool memory and the server kernel's life.
+// ---------------------------------------------------------------------------
+namespace {
+
+// First-fit allocator over [0, size) of a pool, coalescing on release.
+class PoolAlloc {
+  public:
+    void reset(uint64_t size) {
+        free_.clear();
+        if (size)
+            free_[0] = size;
+    }
+    bool alloc(uint64_t n, uint64_t *off) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < n)
+                continue;
+            *off = it->first;
+            const uint64_t at = it->first + n, rest = it->second - n;
+            free_.erase(it);
+            if (rest)
+                free_[at] = rest;
+            return true;
+        }
+        return false;
+    }
+    void release(uint64_t off, uint64_t n) {
+        if (!n)
+            return;
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+  private:
+    std::map<uint64_t, uint64_t> free_;
+};
+
+constexpr uint32_t kMaxGen = (1u << 24) - 1;  // request generations are 24-bit tags
+constexpr uint64_t kDefaultPool = 256ull << 20;
+
+}  // namespace
+
+struct ask_server {
+    ask_ctx *ctx = nullptr;
+    hipStream_t stream = nullptr;
+    uint32_t nslots = 0;
+    uint32_t blocks = 0;
+    ServerSlot *slots = nullptr;
+    ServerCtl *ctl = nullptr;
+    Region *queue = nullptr;
+    RingRec *recs = nullptr;
+    uint64_t queue_entries = 0, rec_entries = 0;
+    ServerMailbox *mb = nullptr;      // host address of the pinned mailbox
+    ServerMailbox *mb_dev = nullptr;  // its device address
+    PoolAlloc qpool, rpool;
+    struct Flight {
+        bool busy = false;
+        bool quarantined = false;  // finished with an error: slot and memory never reused
+        uint64_t ticket = 0;
+        uint32_t gen = 0;
+        uint64_t qoff = 0, qlen = 0, roff = 0, rlen = 0;
+    } flight[kMaxSlots];
+    uint32_t next_gen = 1;
+    uint64_t next_ticket = 1;
+    uint32_t in_flight = 0;
+    bool running = false;
+    std::deque<std::pair<uint64_t, int32_t>> finished;  // reaped, not yet handed out
+    std::unordered_map<uint64_t, int32_t> failed;
+};
+
+namespace {
+
+hipError_t server_launch(ask_server *sv) {
+    ask_ctx *ctx = sv->ctx;
+    // No server kernel runs now: reset the device words, and ring again only
+    // the doorbells of requests posted and not finished.
+    hipError_t e = hipMemsetAsync(sv->ctl, 0, sizeof(ServerCtl), sv->stream);
+    if (e != hipSuccess)
+        return e;
+    __atomic_store_n(&sv->mb->stop, 0u, __ATOMIC_RELAXED);
+    for (uint32_t k = 0; k < kMaxSlots; ++k)
+        if (!sv->flight[k].busy)
+            __atomic_store_n(&sv->mb->doorbell[k], 0u, __ATOMIC_RELAXED);
+    __atomic_thread_fence(__ATOMIC_SEQ_CST);
+    ServerArgs a{};
+    a.slots = sv->slots;
+    a.ctl = sv->ctl;
+    a.nslots = sv->nslots;
+    a.queue = sv->queue;
+    a.recs = sv->recs;
+    a.mb = sv->mb_dev;
+    a.wait_ticks = (uint64_t)(ctx->wait_limit_s * ctx->clock_hz);
+    a.poll_ticks = std::max<uint64_t>(1, (uint64_t)(2e-6 * ctx->clock_hz));
+    a.idle_ticks = (uint64_t)(std::max(1.0, ctx->wait_limit_s) * ctx->clock_hz);
+    e = launch_server(a, sv->blocks, sv->stream);
+    sv->running = e == hipSuccess;
+    return e;
+}
+
+// Move requests whose completion the device has reported to `finished`,
+// returning their pool memory (unless they failed).
+void server_reap(ask_server *sv) {
+    for (uint32_t k = 0; k < sv->nslots; ++k) {
+        ask_server::Flight &f = sv->flight[k];
+        if (!f.busy || __atomic_load_n(&sv->mb->done[k].gen, __ATOMIC_ACQUIRE) != f.gen)
+            continue;
+        const int32_t status = __atomic_load_n(&sv->mb->done[k].status, __ATOMIC_RELAXED);
+        f.busy = false;
+        --sv->in_flight;
+        if (status == ASK_OK) {
+            sv->qpool.release(f.qoff, f.qlen);
+            sv->rpool.release(f.roff, f.rlen);
+        } else {
+            f.quarantined = true;
+            sv->failed[f.ticket] = status;
+        }
+        sv->finished.emplace_back(f.ticket, status);
+    }
+}
+
+// Relaunch the server kernel if it has left (it leaves after a long idle
+// time); requests posted meanwhile are then admitted by the new launch.
+ask_status server_ensure_running(ask_server *sv) {
+    if (sv->running) {
+        const hipError_t q = hipStreamQuery(sv->stream);
+        if (q == hipErrorNotReady)
+            return ASK_OK;
+        if (q != hipSuccess)
+            return hip_fail(sv->ctx, q, "server kernel");
+        sv->running = false;
+        server_reap(sv);
+    }
+    const hipError_t e = server_launch(sv);
+    return e == hipSuccess ? ASK_OK : hip_fail(sv->ctx, e, "server kernel launch");
+}
+
+// Stop the kernel once it has no admitted request and wait for it to leave.
+hipError_t server_stop(ask_server *sv) {
+    __atomic_store_n(&sv->mb->stop, 1u, __ATOMIC_RELEASE);
+    hipError_t e = hipStreamSynchronize(sv->stream);
+    sv->running = false;
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+ask_status ask_server_create(ask_ctx *ctx, const ask_server_cfg *cfg, ask_server **out) {
+    if (!out)
+        return ASK_EINVAL;
+    *out = nullptr;
+    if (!ctx || !cfg || cfg->slots < 1 || cfg->slots > kMaxSlots || cfg->waves_per_cu % 4 != 0)
+        return fail(ctx, ASK_EINVAL, "invalid server configuration%s", nullptr);
+    if (ctx->server)
+        return fail(ctx, ASK_EBUSY, "this context already has a server%s", nullptr);
+    const uint64_t pool = cfg->pool_bytes ? cfg->pool_bytes : kDefaultPool;
+    if (pool < (1ull << 20))
+        return fail(ctx, ASK_EINVAL, "server pool below 1 MiB%s", nullptr);
+    DeviceGuard guard(ctx->device);
+    int occ = 1;
+    if (occupancy_server(&occ) != hipSuccess || occ < 1) {
+        (void)hipGetLastError();
+        occ = 1;
+    }
+    const uint32_t per_cu = cfg->waves_per_cu ? cfg->waves_per_cu / 4 : (uint32_t)std::max(1, occ - 1);
+    if (per_cu > (uint32_t)occ)
+        return fail(ctx, ASK_EINVAL, "waves_per_cu above the server kernel's occupancy%s", nullptr);
+    ask_server *sv = new (std::nothrow) ask_server();
+    if (!sv)
+        return ASK_ENOMEM;
+    sv->ctx = ctx;
+    sv->nslots = cfg->slots;
+    sv->blocks = (uint32_t)ctx->cus * per_cu;
+    // Pool: 1/8 for ring records (32 B), the rest for queue entries (16 B).
+    sv->rec_entries = std::min<uint64_t>(pool / 8 / sizeof(RingRec), 0xffffffffull);
+    sv->queue_entries = std::min<uint64_t>((pool - sv->rec_entries * sizeof(RingRec)) / sizeof(Region),
+                                           0xffffffffull);
+    hipError_t e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&sv->slots, sizeof(ServerSlot) * sv->nslots);
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&sv->ctl, sizeof(ServerCtl));
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&sv->queue, sizeof(Region) * sv->queue_entries);
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&sv->recs, sizeof(RingRec) * sv->rec_entries);
+    if (e == hipSuccess)
+        e = hipMemset(sv->queue, 0, sizeof(Region) * sv->queue_entries);  // no entry carries a generation
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&sv->mb, sizeof(ServerMailbox), hipHostMallocCoherent);
+    if (e == hipSuccess)
+        e = hipHostGetDevicePointer((void **)&sv->mb_dev, sv->mb, 0);
+    if (e == hipSuccess) {
+        memset(sv->mb, 0, sizeof(ServerMailbox));
+        sv->qpool.reset(sv->queue_entries);
+        sv->rpool.reset(sv->rec_entries);
+        e = server_launch(sv);
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        const ask_status st = hip_fail(ctx, e, "server set-up");
+        (void)hipStreamSynchronize(sv->stream);
+        (void)hipFree(sv->slots);
+        (void)hipFree(sv->ctl);
+        (void)hipFree(sv->queue);
+        (void)hipFree(sv->recs);
+        (void)hipHostFree(sv->mb);
+        if (sv->stream)
+            (void)hipStreamDestroy(sv->stream);
+        delete sv;
+        return e == hipErrorOutOfMemory ? ASK_ENOMEM : st;
+    }
+    ctx->server = sv;
+    *out = sv;
+    return ASK_OK;
+}
+
+ask_status ask_server_submit(ask_server *sv, const ask_window *win, const ask_params *params,
+                             uint32_t *d_out, uint64_t *ticket) {
+    if (!sv || !ticket)
+        return ASK_EINVAL;
+    ask_ctx *ctx = sv->ctx;
+    if (check_window(win) != ASK_OK || check_params(win, params) != ASK_OK || !d_out)
+        return fail(ctx, ASK_EINVAL, "invalid window, parameters or output%s", nullptr);
+    const Image im = make_image(win, params, d_out);
+    Bounds b;
+    if (add_bounds(im, b) > (uint32_t)kMaxLevels - 1)
+        return fail(ctx, ASK_EINVAL, "too many levels%s", nullptr);
+    const uint64_t qlen = b.queue_entries(), rlen = b.recs;
+    if (qlen > sv->queue_entries || rlen > sv->rec_entries)
+        return fail(ctx, ASK_ENOMEM, "the request's worst case exceeds the server pool%s", nullptr);
+    DeviceGuard guard(ctx->device);
+    server_reap(sv);
+    if (sv->next_gen > kMaxGen) {
+        // Generations would wrap: once idle, stop, clear the queue pool's
+        // tags and start again from generation 1.
+        if (sv->in_flight)
+            return fail(ctx, ASK_EBUSY, "server restarting%s", nullptr);
+        hipError_t e = server_stop(sv);
+        if (e == hipSuccess)
+            e = hipMemset(sv->queue, 0, sizeof(Region) * sv->queue_entries);
+        if (e != hipSuccess)
+            return hip_fail(ctx, e, "server restart");
+        for (uint32_t k = 0; k < kMaxSlots; ++k)
+            sv->mb->done[k].gen = 0;
+        sv->next_gen = 1;
+    }
+    ask_status st = server_ensure_running(sv);
+    if (st != ASK_OK)
+        return st;
+    uint32_t k = 0;
+    while (k < sv->nslots && (sv->flight[k].busy || sv->flight[k].quarantined))
+        ++k;
+    if (k == sv->nslots)
+        return fail(ctx, ASK_EBUSY, "no free request slot%s", nullptr);
+    uint64_t qoff = 0, roff = 0;
+    if (!sv->qpool.alloc(qlen, &qoff))
+        return fail(ctx, ASK_EBUSY, "not enough free queue memory%s", nullptr);
+    if (rlen && !sv->rpool.alloc(rlen, &roff)) {
+        sv->qpool.release(qoff, qlen);
+        return fail(ctx, ASK_EBUSY, "not enough free record memory%s", nullptr);
+    }
+    const uint32_t gen = sv->next_gen++;
+    ServerPost &p = sv->mb->post[k];
+    p.im = im;
+    p.qoff = (uint32_t)qoff;
+    p.qcap = (uint32_t)qlen;
+    p.roff = (uint32_t)roff;
+    p.rcap = (uint32_t)rlen;
+    __atomic_store_n(&sv->mb->doorbell[k], gen, __ATOMIC_RELEASE);
+    ask_server::Flight &f = sv->flight[k];
+    f.busy = true;
+    f.ticket = sv->next_ticket++;
+    f.gen = gen;
+    f.qoff = qoff;
+    f.qlen = qlen;
+    f.roff = roff;
+    f.rlen = rlen;
+    ++sv->in_flight;
+    *ticket = f.ticket;
+    return ASK_OK;
+}
+
+ask_status ask_server_reap(ask_server *sv, uint64_t *tickets, int32_t *status, uint32_t cap,
+                           uint32_t *n) {
+    if (!sv || !n || (cap && !tickets))
+        return ASK_EINVAL;
+    DeviceGuard guard(sv->ctx->device);
+    server_reap(sv);
+    *n = 0;
+    while (*n < cap && !sv->finished.empty()) {
+        tickets[*n] = sv->finished.front().first;
+        if (status)
+            status[*n] = sv->finished.front().second;
+        sv->finished.pop_front();
+        ++*n;
+    }
+    if (sv->in_flight)
+        return server_ensure_running(sv);
+    return ASK_OK;
+}
+
+ask_status ask_server_poll(ask_server *sv, uint64_t ticket, int *done) {
+    if (!sv || !done || ticket == 0 || ticket >= sv->next_ticket)
+        return ASK_EINVAL;
+    DeviceGuard guard(sv->ctx->device);
+    server_reap(sv);
+    for (uint32_t k = 0; k < sv->nslots; ++k) {
+        if (sv->flight[k].busy && sv->flight[k].ticket == ticket) {
+            *done = 0;
+            return server_ensure_running(sv);
+        }
+    }
+    *done = 1;
+    auto it = sv->failed.find(ticket);
+    return it == sv->failed.end() ? ASK_OK : (ask_status)it->second;
+}
+
+ask_status ask_server_in_flight(const ask_server *sv, uint32_t *n) {
+    if (!sv || !n)
+        return ASK_EINVAL;
+    *n = sv->in_flight;
+    return ASK_OK;
+}
+
+ask_status ask_server_destroy(ask_server *sv) {
+    if (!sv)
+        return ASK_OK;
+    ask_ctx *ctx = sv->ctx;
+    DeviceGuard guard(ctx->device);
+    const auto deadline = std::chrono::steady_clock::now() +
+                          std::chrono::duration<double>(ctx->wait_limit_s + 5.0);
+    while (sv->in_flight && std::chrono::steady_clock::now() < deadline) {
+        server_reap(sv);
+        if (sv->in_flight && server_ensure_running(sv) != ASK_OK)
+            break;
+        std::this_thread::sleep_for(std::chrono::microseconds(50));
+    }
+    const bool late = sv->in_flight != 0;
+    (void)server_stop(sv);
+    (void)hipFree(sv->slots);
+    (void)hipFree(sv->ctl);
+    (void)hipFree(sv->queue);
+    (void)hipFree(sv->recs);
+    (void)hipHostFree(sv->mb);
+    (void)hipStreamDestroy(sv->stream);
+    ctx->server = nullptr;
+    delete sv;
+    return late ? fail(ctx, ASK_ETIMEOUT, "server requests did not finish in time%s", nullptr)
+                : ASK_OK;
 }
 
 }  // extern "C"

@@ -29,12 +29,28 @@ struct Region {
                     // tag is stored last, with release order, and marks the entry valid
 };
 
-// Entry kinds: a region to scan (border query, then fill, leaf or split), or
-// a band of a leaf whose pixels are all computed.
-enum Kind : uint32_t { kScan = 0, kLeaf = 1 };
+// Entry kinds: a region to scan (border query, then fill, leaf or split), a
+// band of a leaf whose pixels are all computed, or one segment of a long
+// ring scanned by several waves (persistent form). A segment entry holds
+// {record index, segment | segments << 16, 0, tag}.
+enum Kind : uint32_t { kScan = 0, kLeaf = 1, kSeg = 2 };
 
 // Pixels per queued leaf task (persistent form).
 constexpr uint32_t kLeafTask = 1024;
+
+// Persistent form: a ring of more than kSegPx pixels is scanned as
+// ceil(ring / kSegPx) segments, each a task of its own.
+constexpr uint32_t kSegPx = 256;
+
+// Shared state of a ring scanned in segments. `v` is the reference dwell
+// (kNoValue until the first segment fixes it), `left` the segments not yet
+// finished, `mixed` nonzero once any segment has found a pixel whose dwell
+// differs from v. The segment that brings `left` to zero decides the region.
+constexpr uint32_t kNoValue = 0xffffffffu;
+struct RingRec {
+    uint32_t img, xy, wh, level;
+    uint32_t v, left, mixed, pad;
+};
 
 __host__ __device__ inline uint32_t pack_xy(uint32_t x, uint32_t y) { return x | (y << 16); }
 __host__ __device__ inline uint32_t pack_wh(uint32_t w, uint32_t h) { return (w - 1) | ((h - 1) << 16); }
@@ -59,6 +75,7 @@ enum Ctrl : uint32_t {
     kTail,                        // persistent queue: next slot to fill
     kPending,                     // persistent queue: regions taken or queued, not finished
     kOverflow,                    // this render: a queue ran out of room
+    kRecs,                        // persistent queue: ring records handed out
     kSticky = 255,                // error bits of all renders since the last check
     kCtrlWords = 256
 };
@@ -76,11 +93,75 @@ struct SubdivArgs {
     Region *out;                // level kernels: regions of the next level
     Region *queue;              // persistent kernel: the queue
     uint32_t cap;               // capacity (entries) of out / queue
+    RingRec *recs;              // persistent kernel: records of segmented rings
+    uint32_t rec_cap;
     uint32_t epoch;
     uint64_t wait_ticks;        // persistent kernel: longest wait, constant-clock ticks
     uint32_t *ctrl;
     DevStats *stats;            // nullptr: do not count
 };
+
+// ---------------------------------------------------------------------------
+// Serving: one persistent kernel takes regions of any admitted request.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kMaxSlots = 64;
+
+// Slot state word: gen << 8 | kind. gen (24 bits, never 0 for a request) is
+// the request's generation; it tags the request's queue entries, so entries
+// left in reused pool memory by earlier requests are never taken for its own.
+enum SlotKind : uint32_t { kSlotFree = 0, kSlotAdmitting = 1, kSlotActive = 2 };
+
+// What the host posts for a request (pinned host memory).
+struct ServerPost {
+    Image im;
+    uint32_t qoff, qcap;  // the request's region queue: entries [qoff, qoff + qcap) of the pool
+    uint32_t roff, rcap;  // its ring records: [roff, roff + rcap) of the record pool
+};
+
+// What the device reports when a request has finished (pinned host memory);
+// gen is written last.
+struct ServerDone {
+    uint32_t gen;
+    int32_t status;
+    unsigned long long ticks;  // constant-clock time of completion
+};
+
+struct ServerMailbox {
+    ServerPost post[kMaxSlots];
+    uint32_t doorbell[kMaxSlots];  // generation of the request last posted in each slot
+    ServerDone done[kMaxSlots];
+    uint32_t stop;                 // nonzero: leave once no request is admitted
+};
+
+// A slot's request, in device memory.
+struct ServerSlot {
+    uint32_t ctrl[kCtrlWords];   // the request's tail, pending, record and error words
+    unsigned long long claim;    // gen << 32 | next queue index to take
+    ServerPost post;             // copy of the request's post
+};
+
+// Device-wide server words.
+struct ServerCtl {
+    uint32_t state[kMaxSlots];
+    unsigned long long next_poll;  // constant-clock time of the next mailbox poll
+    unsigned long long last_busy;  // constant-clock time work was last taken or admitted
+    unsigned long long stop_time;  // constant-clock time the stop flag was first seen, or 0
+};
+
+struct ServerArgs {
+    ServerSlot *slots;
+    ServerCtl *ctl;
+    uint32_t nslots;
+    Region *queue;        // entry pool shared by the requests' queues
+    RingRec *recs;        // record pool
+    ServerMailbox *mb;    // pinned host memory
+    uint64_t wait_ticks;  // longest wait for a claimed entry
+    uint64_t poll_ticks;  // mailbox poll interval
+    uint64_t idle_ticks;  // the kernel leaves after this long with nothing admitted
+};
+
+hipError_t launch_server(const ServerArgs &a, uint32_t grid_blocks, hipStream_t s);
+hipError_t occupancy_server(int *blocks_per_cu);
 
 // Kernel launchers (ask_kernels.hip). All return hipSuccess or the launch error.
 hipError_t launch_exhaustive(const Image &im, hipStream_t s);

@@ -7,6 +7,7 @@
 // the binary64 definition bit for bit.
 #pragma clang fp contract(off)
 
+#include "ask.h"
 #include "ask_internal.hpp"
 
 namespace ask {
@@ -126,6 +127,12 @@ __device__ __forceinline__ bool first_lane() {
     return lane == uniform(lane);
 }
 
+// The constant-rate clock (100 MHz on gfx950), one value for the wave.
+__device__ __forceinline__ unsigned long long clock_now() {
+    const unsigned long long t = __builtin_amdgcn_s_memrealtime();
+    return ((unsigned long long)uniform((uint32_t)(t >> 32)) << 32) | uniform((uint32_t)t);
+}
+
 // One atomic per wave: every lane issues it and only the first active lane
 // contributes (a select, not a branch); every lane gets the old value.
 __device__ __forceinline__ uint32_t wave_add(uint32_t *p, uint32_t v) {
@@ -181,21 +188,58 @@ __global__ __launch_bounds__(kBlock) void exhaustive_kernel(Image im) {
 // pixel_of(i, px, py) names pixel i of the stream (false: no pixel there);
 // done(px, py, dwell) is called by the lane that finished a pixel.
 //
-// Border streams (kBorder) also decide uniformity, and stop as soon as the
-// border is known to be mixed: once some pixel has finished with dwell v,
-// the border is mixed if another pixel finishes with a different dwell, or
-// if a pixel still running has already done v iterations (its dwell is
-// larger than v). The decision is the same as after the whole border; only
-// the remaining iterations are saved. The return value is then false; for a
-// border whose every pixel finished with one value it is true and v holds
-// that value. `partial` receives, per lane, the iterations of a pixel left
-// unfinished by an early stop (work done, for the counters).
+// Border streams (an active border policy) also decide uniformity, and stop
+// as soon as the border is known to be mixed: once some pixel has finished
+// with dwell v (the policy fixes v: this wave's first, or the first of any
+// segment of the ring), the border is mixed if another pixel finishes with a
+// different dwell, if a pixel still running has already done v iterations
+// (its dwell is larger than v), or if the policy reports that another
+// segment found it mixed. The decision is the same as after the whole
+// border; only the remaining iterations are saved. The return value is then
+// false; for a border whose every pixel finished with v it is true.
+// `partial` receives, per lane, the iterations of a pixel left unfinished by
+// an early stop (work done, for the counters).
 // ---------------------------------------------------------------------------
 constexpr uint32_t kRoundBlocks = 2;
 
-template <bool kBorder, class PixelOf, class Done>
+// Border policies of dwell_stream. A leaf stream has none; a ring scanned by
+// one wave takes the first finished dwell as its reference; a ring segment
+// shares the reference and the "mixed" verdict with the other segments of
+// its ring through the ring's record.
+struct NoBorder {
+    static constexpr bool kActive = false;
+    __device__ uint32_t settle(uint32_t v) const { return v; }
+    __device__ bool stopped() const { return false; }
+};
+
+struct WaveBorder {
+    static constexpr bool kActive = true;
+    __device__ uint32_t settle(uint32_t v) const { return v; }
+    __device__ bool stopped() const { return false; }
+};
+
+struct SharedBorder {
+    static constexpr bool kActive = true;
+    RingRec *rec;
+    // The first segment to finish a pixel publishes that dwell; every
+    // segment compares against the published value.
+    __device__ uint32_t settle(uint32_t v) const {
+        uint32_t old = kNoValue;
+        if (first_lane())
+            old = atomicCAS(&rec->v, kNoValue, v);
+        old = uniform(old);
+        return old == kNoValue ? v : old;
+    }
+    __device__ bool stopped() const {
+        return uniform(__hip_atomic_load(&rec->mixed, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT)) != 0;
+    }
+};
+
+template <class Border, class PixelOf, class Done>
 __device__ __forceinline__ bool dwell_stream(const Image &im, uint32_t n, PixelOf pixel_of,
-                                             Done done, uint32_t &v, uint32_t &partial) {
+                                             Done done, const Border &border, uint32_t &v,
+                                             uint32_t &partial) {
     const uint32_t D = im.D;
     uint32_t next = 0;  // first stream index no lane has taken yet (uniform)
     bool have = false, special = false, vset = false;
@@ -217,8 +261,11 @@ __device__ __forceinline__ bool dwell_stream(const Image &im, uint32_t n, PixelO
             }
             next = min(n, next + (uint32_t)__popcll(idle));
         }
-        if (__ballot(have) == 0)
-            break;
+        if (__ballot(have) == 0) {
+            if (next >= n)
+                break;
+            continue;  // this batch named no pixel (skipped positions): take the next
+        }
         uint32_t dw = 0;
         bool fin = false;
         if (have) {
@@ -271,12 +318,12 @@ __device__ __forceinline__ bool dwell_stream(const Image &im, uint32_t n, PixelO
                 have = false;
             }
         }
-        if (kBorder) {
+        if (Border::kActive) {
             if (!vset && __ballot(fin)) {
-                v = uniform(wave_min(fin ? dw : 0xffffffffu));
+                v = border.settle(uniform(wave_min(fin ? dw : 0xffffffffu)));
                 vset = true;
             }
-            if (vset && __ballot((fin && dw != v) || (have && kbase >= v))) {
+            if (vset && (__ballot((fin && dw != v) || (have && kbase >= v)) || border.stopped())) {
                 partial = have ? kbase : 0u;
                 return false;
             }
@@ -348,7 +395,7 @@ __device__ unsigned long long leaf_region(const Image &im, uint32_t x, uint32_t 
                                           uint32_t h) {
     unsigned long long it = 0;
     uint32_t v, partial;
-    dwell_stream<false>(
+    dwell_stream(
         im, w * h,
         [&](uint32_t i, uint32_t &px, uint32_t &py) {
             const uint32_t row = i / w;
@@ -360,7 +407,7 @@ __device__ unsigned long long leaf_region(const Image &im, uint32_t x, uint32_t 
             im.out[(size_t)py * im.W + px] = d;
             it += d;
         },
-        v, partial);
+        NoBorder{}, v, partial);
     return it;
 }
 
@@ -368,24 +415,24 @@ __device__ __forceinline__ Image image_of(const SubdivArgs &a, uint32_t img) {
     return a.table ? a.table[img] : a.single;
 }
 
-// Append `count` rectangles (rect_of(j, x0, y0, x1, y1) -> false for an
-// empty one) to the next level (per-level form) or to the queue (persistent
-// form) as entries of the given kind, with one atomic add per wave and per
-// 64 entries: a ballot of the non-empty rectangles and their rank give every
-// entry its slot (Sec. 5.3.1, compact insertion).
-template <bool kQueue, class RectOf>
-__device__ void emit_rects(const SubdivArgs &a, uint32_t img, uint32_t count, uint32_t kind,
-                           uint32_t level, uint32_t lane, RectOf rect_of) {
-    const uint32_t tag = (a.epoch << 8) | (kind << 6) | (level + 1);
+// Append `count` entries (entry_of(j, e) fills e's img, xy and wh, or
+// returns false for an empty one) to the next level's table (per-level form)
+// or to the queue (persistent form) with the given kind and level, using one
+// atomic add per wave and per 64 entries: a ballot of the non-empty entries
+// and their rank give every entry its slot (Sec. 5.3.1, compact insertion).
+template <bool kQueue, class EntryOf>
+__device__ void emit_entries(const SubdivArgs &a, uint32_t count, uint32_t kind, uint32_t level,
+                             uint32_t lane, EntryOf entry_of) {
+    const uint32_t tag = (a.epoch << 8) | (kind << 6) | level;
     for (uint32_t base = 0; base < count; base += kWave) {
         const uint32_t j = base + lane;
-        uint32_t cx0 = 0, cx1 = 0, cy0 = 0, cy1 = 0;
-        const bool ok = j < count && rect_of(j, cx0, cy0, cx1, cy1);
+        Region e{0, 0, 0, tag};
+        const bool ok = j < count && entry_of(j, e);
         const unsigned long long mask = __ballot(ok);
         const uint32_t n = (uint32_t)__popcll(mask);
         if (n == 0)
             continue;
-        const uint32_t slot0 = wave_add(kQueue ? &a.ctrl[kTail] : &a.ctrl[kCount + level + 1], n);
+        const uint32_t slot0 = wave_add(kQueue ? &a.ctrl[kTail] : &a.ctrl[kCount + level], n);
         const bool fits = (uint64_t)slot0 + n <= a.cap;
         if (fits) {
             if (kQueue)
@@ -397,13 +444,13 @@ __device__ void emit_rects(const SubdivArgs &a, uint32_t img, uint32_t count, ui
         if (ok && fits) {
             const uint32_t slot = slot0 + lane_rank(mask);
             if (kQueue) {
-                Region *e = a.queue + slot;
-                e->img = img;
-                e->xy = pack_xy(cx0, cy0);
-                e->wh = pack_wh(cx1 - cx0, cy1 - cy0);
-                __hip_atomic_store(&e->tag, tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                Region *q = a.queue + slot;
+                q->img = e.img;
+                q->xy = e.xy;
+                q->wh = e.wh;
+                __hip_atomic_store(&q->tag, tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             } else {
-                a.out[slot] = Region{img, pack_xy(cx0, cy0), pack_wh(cx1 - cx0, cy1 - cy0), tag};
+                a.out[slot] = e;
             }
         }
     }
@@ -414,74 +461,44 @@ __device__ void emit_rects(const SubdivArgs &a, uint32_t img, uint32_t count, ui
 template <bool kQueue>
 __device__ void split_region(const SubdivArgs &a, uint32_t img, uint32_t x, uint32_t y,
                              uint32_t w, uint32_t h, uint32_t r, uint32_t level, uint32_t lane) {
-    emit_rects<kQueue>(a, img, r * r, kScan, level, lane,
-                       [&](uint32_t j, uint32_t &x0, uint32_t &y0, uint32_t &x1, uint32_t &y1) {
-                           const uint32_t jx = j % r, jy = j / r;
-                           x0 = x + (uint32_t)(((uint64_t)jx * w) / r);
-                           x1 = x + (uint32_t)(((uint64_t)(jx + 1) * w) / r);
-                           y0 = y + (uint32_t)(((uint64_t)jy * h) / r);
-                           y1 = y + (uint32_t)(((uint64_t)(jy + 1) * h) / r);
-                           return x1 > x0 && y1 > y0;
-                       });
+    emit_entries<kQueue>(a, r * r, kScan, level + 1, lane, [&](uint32_t j, Region &e) {
+        const uint32_t jx = j % r, jy = j / r;
+        const uint32_t x0 = x + (uint32_t)(((uint64_t)jx * w) / r);
+        const uint32_t x1 = x + (uint32_t)(((uint64_t)(jx + 1) * w) / r);
+        const uint32_t y0 = y + (uint32_t)(((uint64_t)jy * h) / r);
+        const uint32_t y1 = y + (uint32_t)(((uint64_t)(jy + 1) * h) / r);
+        e.img = img;
+        e.xy = pack_xy(x0, y0);
+        e.wh = pack_wh(x1 - x0, y1 - y0);
+        return x1 > x0 && y1 > y0;
+    });
 }
 
 // Persistent form: the per-pixel work of a leaf becomes row bands of about
 // kLeafTask pixels, queued as leaf tasks that any wave can take, so that no
 // wave holds a whole leaf while the others idle.
-template <bool kQueue>
 __device__ void queue_leaf_bands(const SubdivArgs &a, uint32_t img, uint32_t x, uint32_t y,
                                  uint32_t w, uint32_t h, uint32_t level, uint32_t lane) {
     const uint32_t hb = max(1u, kLeafTask / w);
     const uint32_t nb = (h + hb - 1) / hb;
-    emit_rects<kQueue>(a, img, nb, kLeaf, level - 1, lane,
-                       [&](uint32_t j, uint32_t &x0, uint32_t &y0, uint32_t &x1, uint32_t &y1) {
-                           x0 = x;
-                           x1 = x + w;
-                           y0 = y + j * hb;
-                           y1 = min(y + h, y0 + hb);
-                           return true;
-                       });
+    emit_entries<true>(a, nb, kLeaf, level, lane, [&](uint32_t j, Region &e) {
+        const uint32_t y0 = y + j * hb;
+        e.img = img;
+        e.xy = pack_xy(x, y0);
+        e.wh = pack_wh(w, min(y + h, y0 + hb) - y0);
+        return true;
+    });
 }
 
-// One region, by one wave: border query Q, then fill T, leaf L or split S
-// (Sec. 4.2.1).
+// What follows the border query of a region (Sec. 4.2.1): fill T when the
+// ring is uniform, else leaf L at size B, else split S.
 template <bool kQueue>
-__device__ void process_region(const SubdivArgs &a, const Region &R, uint32_t lane) {
-    const uint32_t img = uniform(R.img), xy = uniform(R.xy), wh = uniform(R.wh);
-    const uint32_t tag = uniform(R.tag);
-    const uint32_t level = tag & 0x3fu, kind = (tag >> 6) & 0x3u;
-    const Image im = image_of(a, img);
-    const uint32_t x = xy & 0xffffu, y = xy >> 16;
-    const uint32_t w = (wh & 0xffffu) + 1, h = (wh >> 16) + 1;
+__device__ void decide_region(const SubdivArgs &a, uint32_t img, const Image &im, uint32_t x,
+                              uint32_t y, uint32_t w, uint32_t h, uint32_t level,
+                              bool uniform_ring, uint32_t v, uint32_t lane) {
     DevStats *st = a.stats;
-    if (kind == kLeaf) {  // a band of a leaf decided earlier: every pixel
-        unsigned long long li = leaf_region(im, x, y, w, h);
-        if (st)
-            wave_add64(&st->iters_leaf, wave_sum(li));
-        return;
-    }
-
-    // Q: the ring's dwells, in a spread order (the first 64 pixels are spaced
-    // evenly around the ring, the next 64 follow them, ...), until the ring
-    // is known to be mixed or has been computed whole.
-    const uint32_t nring = ring_size(w, h);
-    const uint32_t q = (nring + kWave - 1) / kWave;
-    unsigned long long it = 0;
-    uint32_t v = 0, partial = 0;
-    const bool uniform_ring = dwell_stream<true>(
-        im, q * kWave,
-        [&](uint32_t j, uint32_t &px, uint32_t &py) {
-            const uint32_t t = (j % kWave) * q + j / kWave;
-            if (t >= nring)
-                return false;
-            ring_pixel(x, y, w, h, t, px, py);
-            return true;
-        },
-        [&](uint32_t, uint32_t, uint32_t d) { it += d; }, v, partial);
     if (st) {
-        it = wave_sum(it + partial);
         wave_add64(&st->regions[level], 1ull);
-        wave_add64(&st->iters_ring, it);
         wave_max(&st->levels, level + 1);
     }
     if (uniform_ring) {
@@ -494,7 +511,7 @@ __device__ void process_region(const SubdivArgs &a, const Region &R, uint32_t la
         if (st)
             wave_add64(&st->leaves[level], 1ull);
         if (kQueue && w * h > kLeafTask) {
-            queue_leaf_bands<kQueue>(a, img, x, y, w, h, level, lane);
+            queue_leaf_bands(a, img, x, y, w, h, level, lane);
             return;
         }
         unsigned long long li = leaf_region(im, x, y, w, h);
@@ -510,6 +527,124 @@ __device__ void process_region(const SubdivArgs &a, const Region &R, uint32_t la
     split_region<kQueue>(a, img, x, y, w, h, im.r, level, lane);
     if (st)
         wave_add64(&st->splits[level], 1ull);
+}
+
+// Q over the ring pixels t = s, s + step, s + 2 step, ... (all of them for
+// s = 0, step = 1), leaving out the multiples of `skip` when skip > 0, taken
+// in a spread order: the first 64 are spaced evenly over the list, the next
+// 64 follow them, and so on. Returns whether every one finished with dwell
+// v; adds the iterations done to the counters.
+template <class Border>
+__device__ bool scan_ring(const SubdivArgs &a, const Image &im, uint32_t x, uint32_t y,
+                          uint32_t w, uint32_t h, uint32_t s, uint32_t step, uint32_t skip,
+                          const Border &border, uint32_t &v) {
+    const uint32_t nring = ring_size(w, h);
+    const uint32_t m = (nring - s + step - 1) / step;
+    const uint32_t q = (m + kWave - 1) / kWave;
+    unsigned long long it = 0;
+    uint32_t partial = 0;
+    const bool same = dwell_stream(
+        im, q * kWave,
+        [&](uint32_t j, uint32_t &px, uint32_t &py) {
+            const uint32_t i = (j % kWave) * q + j / kWave;
+            const uint32_t t = s + i * step;
+            if (i >= m || (skip && t % skip == 0))
+                return false;
+            ring_pixel(x, y, w, h, t, px, py);
+            return true;
+        },
+        [&](uint32_t, uint32_t, uint32_t d) { it += d; }, border, v, partial);
+    if (a.stats)
+        wave_add64(&a.stats->iters_ring, wave_sum(it + partial));
+    return same;
+}
+
+// Stride of the probe of a long ring: its pixels 0, p, 2p, ... (at most 64).
+__device__ __forceinline__ uint32_t probe_stride(uint32_t nring) {
+    return (nring + kWave - 1) / kWave;
+}
+
+// One segment of a segmented ring: scan its pixels, publish a mixed verdict,
+// and, as the ring's last segment to finish, decide the region.
+__device__ void scan_segment(const SubdivArgs &a, uint32_t rid, uint32_t seg, uint32_t nseg,
+                             uint32_t lane) {
+    RingRec *rec = a.recs + rid;
+    const uint32_t img = uniform(rec->img), xy = uniform(rec->xy), wh = uniform(rec->wh);
+    const uint32_t level = uniform(rec->level);
+    const Image im = image_of(a, img);
+    const uint32_t x = xy & 0xffffu, y = xy >> 16;
+    const uint32_t w = (wh & 0xffffu) + 1, h = (wh >> 16) + 1;
+    uint32_t v = 0;
+    if (!scan_ring(a, im, x, y, w, h, seg, nseg, probe_stride(ring_size(w, h)), SharedBorder{rec}, v))
+        __hip_atomic_store(&rec->mixed, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // The count-down releases this wave's verdict and, for the last segment,
+    // acquires every other segment's.
+    uint32_t left = 0;
+    if (first_lane())
+        left = __hip_atomic_fetch_add(&rec->left, (uint32_t)-1, __ATOMIC_ACQ_REL,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+    if (uniform(left) != 1u)
+        return;
+    const bool mixed = uniform(__hip_atomic_load(&rec->mixed, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT)) != 0;
+    const uint32_t vv = uniform(__hip_atomic_load(&rec->v, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT));
+    decide_region<true>(a, img, im, x, y, w, h, level, !mixed, vv, lane);
+}
+
+// One region, by one wave: border query Q, then fill T, leaf L or split S
+// (Sec. 4.2.1). In the persistent form a ring longer than kSegPx pixels is
+// first probed at 64 evenly spaced pixels; a mixed probe decides at once,
+// and a uniform one (a likely fill, with no children to wait for) cuts the
+// rest of the ring into segments: this wave scans the first, the others go
+// to the queue.
+template <bool kQueue>
+__device__ void process_region(const SubdivArgs &a, const Region &R, uint32_t lane) {
+    const uint32_t img = uniform(R.img), xy = uniform(R.xy), wh = uniform(R.wh);
+    const uint32_t tag = uniform(R.tag);
+    const uint32_t level = tag & 0x3fu, kind = (tag >> 6) & 0x3u;
+    if (kQueue && kind == kSeg) {
+        scan_segment(a, img, xy & 0xffffu, xy >> 16, lane);
+        return;
+    }
+    const Image im = image_of(a, img);
+    const uint32_t x = xy & 0xffffu, y = xy >> 16;
+    const uint32_t w = (wh & 0xffffu) + 1, h = (wh >> 16) + 1;
+    if (kind == kLeaf) {  // a band of a leaf decided earlier: every pixel
+        unsigned long long li = leaf_region(im, x, y, w, h);
+        if (a.stats)
+            wave_add64(&a.stats->iters_leaf, wave_sum(li));
+        return;
+    }
+    const uint32_t nring = ring_size(w, h);
+    uint32_t v = 0;
+    if (kQueue && nring > kSegPx) {
+        const uint32_t p = probe_stride(nring);
+        if (!scan_ring(a, im, x, y, w, h, 0, p, 0, WaveBorder{}, v)) {
+            decide_region<kQueue>(a, img, im, x, y, w, h, level, false, v, lane);
+            return;
+        }
+        const uint32_t nseg = (nring + kSegPx - 1) / kSegPx;
+        const uint32_t rid = wave_add(&a.ctrl[kRecs], 1u);
+        if (rid >= a.rec_cap) {  // the host sizes the records; never write past them
+            wave_or(&a.ctrl[kOverflow], 4u);
+            wave_or(&a.ctrl[kSticky], kErrOverflow);
+            return;
+        }
+        RingRec *rec = a.recs + rid;
+        *rec = RingRec{img, xy, wh, level, v, nseg, 0u, 0u};
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        emit_entries<true>(a, nseg - 1, kSeg, level, lane, [&](uint32_t j, Region &e) {
+            e.img = rid;
+            e.xy = (j + 1) | (nseg << 16);
+            e.wh = 0;
+            return true;
+        });
+        scan_segment(a, rid, 0, nseg, lane);
+        return;
+    }
+    const bool same = scan_ring(a, im, x, y, w, h, 0, 1, 0, WaveBorder{}, v);
+    decide_region<kQueue>(a, img, im, x, y, w, h, level, same, v, lane);
 }
 
 // Per-level kernel: waves take the level's regions one at a time through an
@@ -559,7 +694,7 @@ __global__ __launch_bounds__(kBlock) void persistent_kernel(SubdivArgs a) {
     for (;;) {
         // Every lane runs the wait; the values it reads are made uniform.
         const uint32_t idx = wave_add(&ctrl[kHead], 1u);
-        const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+        const uint64_t t0 = clock_now();
         uint32_t nap = 1, polls = 0;
         bool ready = false;
         for (;;) {
@@ -576,7 +711,7 @@ __global__ __launch_bounds__(kBlock) void persistent_kernel(SubdivArgs a) {
                 if (uniform(__hip_atomic_load(&ctrl[kPending], __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_AGENT)) == 0)
                     break;
-                if (__builtin_amdgcn_s_memrealtime() - t0 > a.wait_ticks) {
+                if (clock_now() - t0 > a.wait_ticks) {
                     wave_or(&ctrl[kSticky], kErrTimeout);
                     break;
                 }
@@ -588,6 +723,270 @@ __global__ __launch_bounds__(kBlock) void persistent_kernel(SubdivArgs a) {
             return;
         process_region<true>(a, a.queue[idx], lane);
         wave_add(&ctrl[kPending], (uint32_t)-1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Serving kernel: continuous batching into one persistent kernel.
+//
+// Every wave loops: take a region of the oldest admitted request that has
+// one (a compare-and-swap on that request's {gen, head} word, so a wave that
+// read a slot before it was reused can never take an entry of the slot's
+// next request), process it exactly as the persistent kernel does, with the
+// request's own queue, records and counters, and count it done. Between
+// regions, one wave at a time (at most every poll_ticks) reads the host's
+// mailbox and admits posted requests into free slots. The wave that counts a
+// request's last region done reports the request to the host.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long uniform64(unsigned long long v) {
+    return ((unsigned long long)uniform((uint32_t)(v >> 32)) << 32) | uniform((uint32_t)v);
+}
+
+__device__ __forceinline__ uint32_t slot_gen(uint32_t st) { return st >> 8; }
+__device__ __forceinline__ uint32_t slot_kind(uint32_t st) { return st & 0xffu; }
+
+// A struct that the host or other waves write while the kernel runs, read
+// whole by one wave: one 32-bit word per lane with a relaxed atomic load (a
+// vector load, never through the scalar cache), then each word made uniform.
+// Every lane of the wave must be active.
+template <class T, int kScope>
+__device__ __forceinline__ T load_words(const T *p) {
+    constexpr uint32_t nw = sizeof(T) / 4;
+    static_assert(sizeof(T) % 4 == 0 && nw <= (uint32_t)kWave, "one word per lane");
+    const uint32_t lane = __lane_id();
+    const uint32_t *w = reinterpret_cast<const uint32_t *>(p);
+    const uint32_t v = lane < nw ? __hip_atomic_load(w + lane, __ATOMIC_RELAXED, kScope) : 0u;
+    T out;
+    uint32_t *o = reinterpret_cast<uint32_t *>(&out);
+#pragma unroll
+    for (uint32_t i = 0; i < nw; ++i)
+        o[i] = __builtin_amdgcn_readlane(v, i);
+    return out;
+}
+
+template <class T>
+__device__ __forceinline__ void store_words(T *p, const T &v) {
+    constexpr uint32_t nw = sizeof(T) / 4;
+    static_assert(sizeof(T) % 4 == 0 && nw <= (uint32_t)kWave, "one word per lane");
+    const uint32_t lane = __lane_id();
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(&v);
+    uint32_t word = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < nw; ++i)
+        word = lane == i ? src[i] : word;
+    if (lane < nw)
+        reinterpret_cast<uint32_t *>(p)[lane] = word;
+}
+
+// The request in a slot as subdivision arguments.
+__device__ __forceinline__ SubdivArgs slot_args(const ServerArgs &sa, ServerSlot *sl,
+                                                const ServerPost &post, uint32_t gen) {
+    SubdivArgs a{};
+    a.single = post.im;
+    a.nimg = 1;
+    a.queue = sa.queue + post.qoff;
+    a.cap = post.qcap;
+    a.recs = sa.recs + post.roff;
+    a.rec_cap = post.rcap;
+    a.epoch = gen;
+    a.wait_ticks = sa.wait_ticks;
+    a.ctrl = sl->ctrl;
+    return a;
+}
+
+// Admit the request posted in slot k (this wave holds the slot in
+// kSlotAdmitting): copy its post, set its counters, write its level-0
+// regions (the g x g floor partition) into its queue, then publish the slot.
+__device__ void admit(const ServerArgs &sa, uint32_t k, uint32_t gen, uint32_t lane) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // the post was written before its doorbell
+    const ServerPost post = load_words<ServerPost, __HIP_MEMORY_SCOPE_SYSTEM>(&sa.mb->post[k]);
+    ServerSlot *sl = sa.slots + k;
+    store_words(&sl->post, post);
+    const Image &im = post.im;
+    const uint32_t g = im.g, nseed = g * g;
+    for (uint32_t i = lane; i < kCtrlWords; i += kWave)
+        sl->ctrl[i] = (i == kTail || i == kPending) ? nseed : 0u;
+    sl->claim = (unsigned long long)gen << 32;
+    Region *q = sa.queue + post.qoff;
+    for (uint32_t j = lane; j < nseed; j += kWave) {
+        const uint32_t jx = j % g, jy = j / g;
+        const uint32_t x0 = (uint32_t)(((uint64_t)jx * im.W) / g);
+        const uint32_t x1 = (uint32_t)(((uint64_t)(jx + 1) * im.W) / g);
+        const uint32_t y0 = (uint32_t)(((uint64_t)jy * im.H) / g);
+        const uint32_t y1 = (uint32_t)(((uint64_t)(jy + 1) * im.H) / g);
+        q[j] = Region{0, pack_xy(x0, y0), pack_wh(x1 - x0, y1 - y0), gen << 8};
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(&sa.ctl->state[k], (gen << 8) | kSlotActive, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Read the doorbells and admit every request posted in a free slot. Returns
+// whether one was admitted. Also turns the host's stop flag into a device
+// word that every wave can read cheaply.
+__device__ bool poll_mailbox(const ServerArgs &sa, uint32_t lane) {
+    if (uniform(__hip_atomic_load(&sa.mb->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))) {
+        const unsigned long long t = clock_now() | 1ull;
+        if (first_lane())
+            atomicCAS(&sa.ctl->stop_time, 0ull, t);
+        return false;
+    }
+    uint32_t posted = 0, st = 0;
+    if (lane < sa.nslots) {
+        posted = __hip_atomic_load(&sa.mb->doorbell[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        st = __hip_atomic_load(&sa.ctl->state[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    unsigned long long mask =
+        __ballot(posted != 0 && slot_kind(st) == kSlotFree && posted != slot_gen(st));
+    bool any = false;
+    while (mask) {
+        const uint32_t k = uniform((uint32_t)__builtin_ctzll(mask));
+        mask &= mask - 1;
+        const uint32_t gen = __builtin_amdgcn_readlane(posted, k);
+        const uint32_t stk = __builtin_amdgcn_readlane(st, k);
+        uint32_t old = ~stk;
+        if (first_lane())
+            old = atomicCAS(&sa.ctl->state[k], stk, (gen << 8) | kSlotAdmitting);
+        if (uniform(old) != stk)
+            continue;
+        admit(sa, k, gen, lane);
+        any = true;
+    }
+    return any;
+}
+
+// Report request k as finished: free its slot for the next admission, then
+// make its image visible beyond the device and tell the host.
+__device__ void finish_request(const ServerArgs &sa, ServerSlot *sl, uint32_t k, uint32_t gen) {
+    const uint32_t err = uniform(__hip_atomic_load(&sl->ctrl[kSticky], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT));
+    const int32_t status = (err & kErrTimeout)    ? (int32_t)ASK_ETIMEOUT
+                           : (err & kErrOverflow) ? (int32_t)ASK_EOVERFLOW
+                                                  : (int32_t)ASK_OK;
+    __hip_atomic_store(&sa.ctl->state[k], (gen << 8) | kSlotFree, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long t = clock_now();
+    if (first_lane()) {
+        ServerDone *d = &sa.mb->done[k];
+        __hip_atomic_store(&d->status, status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&d->ticks, t,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+        __hip_atomic_store(&d->gen, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+// Process entry idx of request k (generation gen), taken by this wave.
+__device__ void serve_entry(const ServerArgs &sa, uint32_t k, uint32_t gen, uint32_t idx,
+                            uint32_t lane) {
+    ServerSlot *sl = sa.slots + k;
+    const ServerPost post = load_words<ServerPost, __HIP_MEMORY_SCOPE_AGENT>(&sl->post);
+    const SubdivArgs a = slot_args(sa, sl, post, gen);
+    // The entry is below the tail, so its producer has reserved it; wait
+    // until it is written.
+    const uint64_t t0 = clock_now();
+    uint32_t nap = 1;
+    bool ready = false;
+    for (;;) {
+        const uint32_t t = uniform(__hip_atomic_load(&a.queue[idx].tag, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT));
+        if ((t >> 8) == gen) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            ready = true;
+            break;
+        }
+        if (clock_now() - t0 > a.wait_ticks)
+            break;
+        pause(nap);
+        nap = min(nap * 2, 32u);
+    }
+    if (ready)
+        process_region<true>(a, a.queue[idx], lane);
+    else
+        wave_or(&sl->ctrl[kSticky], kErrTimeout);
+    // Count the entry done, releasing this wave's writes; the last one also
+    // acquires everyone else's.
+    uint32_t left = 0;
+    if (first_lane())
+        left = __hip_atomic_fetch_add(&sl->ctrl[kPending], (uint32_t)-1, __ATOMIC_ACQ_REL,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+    if (uniform(left) == 1u)
+        finish_request(sa, sl, k, gen);
+}
+
+__global__ __launch_bounds__(kBlock) void server_kernel(ServerArgs sa) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    uint32_t nap = 1;
+    const unsigned long long t0 = clock_now();
+    if (first_lane())  // the idle clock starts with the first wave
+        atomicCAS(&sa.ctl->last_busy, 0ull, t0);
+    for (;;) {
+        // Mailbox, at most every poll_ticks over the whole grid.
+        const unsigned long long now = clock_now();
+        const unsigned long long due = uniform64(
+            __hip_atomic_load(&sa.ctl->next_poll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (now >= due) {
+            unsigned long long old = ~due;
+            if (first_lane())
+                old = atomicCAS(&sa.ctl->next_poll, due, now + sa.poll_ticks);
+            if (uniform64(old) == due && poll_mailbox(sa, lane)) {
+                __hip_atomic_store(&sa.ctl->last_busy, now, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                nap = 1;
+            }
+        }
+        // Lane k looks at slot k: active, of its generation, and with an
+        // entry reserved below the tail (and inside the queue) not yet taken.
+        uint32_t st = 0, lim = 0;
+        unsigned long long hc = 0;
+        if (lane < sa.nslots) {
+            st = __hip_atomic_load(&sa.ctl->state[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (slot_kind(st) == kSlotActive) {
+                ServerSlot *sl = sa.slots + lane;
+                hc = __hip_atomic_load(&sl->claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                lim = min(__hip_atomic_load(&sl->ctrl[kTail], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                          __hip_atomic_load(&sl->post.qcap, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            }
+        }
+        const bool avail = slot_kind(st) == kSlotActive && (uint32_t)(hc >> 32) == slot_gen(st) &&
+                           (uint32_t)hc < lim;
+        if (__ballot(avail)) {
+            // The oldest request first: the least generation (the host hands
+            // them out in order and restarts the server before they wrap).
+            const uint32_t oldest = uniform(wave_min(avail ? slot_gen(st) : 0xffffffffu));
+            const uint32_t k = uniform((uint32_t)__builtin_ctzll(__ballot(avail && slot_gen(st) == oldest)));
+            const unsigned long long hk =
+                ((unsigned long long)__builtin_amdgcn_readlane((uint32_t)(hc >> 32), k) << 32) |
+                __builtin_amdgcn_readlane((uint32_t)hc, k);
+            unsigned long long old = ~hk;
+            if (first_lane())
+                old = atomicCAS(&sa.slots[k].claim, hk, hk + 1);
+            if (uniform64(old) != hk)
+                continue;  // another wave took it first: look again
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the slot's post and counters
+            serve_entry(sa, k, (uint32_t)(hk >> 32), (uint32_t)hk, lane);
+            __hip_atomic_store(&sa.ctl->last_busy, clock_now(),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            nap = 1;
+            continue;
+        }
+        // Nothing to take. Leave when stopped, or idle for idle_ticks, with no
+        // request admitted or being admitted, or stopped for wait_ticks in
+        // any case (a request that cannot finish never holds the grid);
+        // otherwise rest a little longer each time.
+        const unsigned long long t = clock_now();
+        const unsigned long long stop_time = uniform64(
+            __hip_atomic_load(&sa.ctl->stop_time, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        const unsigned long long busy = uniform64(
+            __hip_atomic_load(&sa.ctl->last_busy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        const bool none = __ballot(slot_kind(st) != kSlotFree) == 0;
+        // (The times were taken by other waves and may be a little later
+        // than t.)
+        const unsigned long long since_stop = t > stop_time ? t - stop_time : 0;
+        const unsigned long long since_busy = t > busy ? t - busy : 0;
+        if ((stop_time && (none || since_stop > sa.wait_ticks)) || (none && since_busy > sa.idle_ticks))
+            return;
+        pause(nap);
+        nap = min(nap * 2, 256u);
     }
 }
 
@@ -692,6 +1091,15 @@ hipError_t launch_persistent(const SubdivArgs &a, uint32_t grid_blocks, hipStrea
 
 hipError_t occupancy_level(int *blocks_per_cu) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, level_kernel, kBlock, 0);
+}
+
+hipError_t launch_server(const ServerArgs &a, uint32_t grid_blocks, hipStream_t s) {
+    hipLaunchKernelGGL(server_kernel, dim3(grid_blocks), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t occupancy_server(int *blocks_per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, server_kernel, kBlock, 0);
 }
 
 hipError_t occupancy_persistent(int *blocks_per_cu) {

@@ -174,6 +174,36 @@ def test_subdiv_without_stats_equals_with_stats(gpu):
         assert np.array_equal(a, b)
 
 
+# Windows whose 180 x 150 border (one level-0 region at g = 1) is mixed while
+# every 11th border pixel, counted along the ring (first row, last row, first
+# column, last column), has one dwell: a long ring's first 64 evenly spaced
+# pixels then agree, and only the rest of the ring shows that it is mixed.
+PROBE_UNIFORM_WINDOWS = [
+    Window(-0.70645, -0.18018, -0.18604, 0.25252, 180, 150, 96),
+    Window(0.21974, 0.30202, -0.44334, -0.37477, 180, 150, 96),
+    Window(0.15577, 0.32353, 0.04127, 0.18107, 180, 150, 96),
+]
+
+
+def _ring_dwells(E):
+    H, W = E.shape
+    return np.concatenate([E[0, :], E[H - 1, :], E[1:H - 1, 0], E[1:H - 1, W - 1]])
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_mixed_ring_whose_spread_sample_is_uniform(gpu, ref, form):
+    for w in PROBE_UNIFORM_WINDOWS:
+        E, _ = ref.exhaustive(w)
+        ring = _ring_dwells(np.asarray(E).reshape(w.H, w.W))
+        p = (len(ring) + 63) // 64
+        assert len(np.unique(ring[::p])) == 1 and len(np.unique(ring)) > 1
+        for B in (16, 64):
+            want, ref_st = ref.subdiv(w, 1, 2, B)
+            img, st = gpu_subdiv(gpu, w, 1, 2, B, form)
+            assert np.array_equal(img, want), (w, B)
+            assert_same_stats(st, ref_st)
+
+
 def test_persistent_repeated_calls(gpu, ref):
     # Queue slots are reused across calls; tags of older calls must never be
     # taken for new entries.
