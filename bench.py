@@ -13,7 +13,12 @@ Printed as one JSON line:
              dwell iteration actually computed, over the kernel's own device
              time (HIP events recorded by the library on the render's stream)
   forms      the exhaustive kernel and the per-level (ASK) form on the same
-             image, for the speedups
+             image, for the speedups; the batched workload (256 images of
+             uneven size and zoom centred on boundary points, one
+             persistent launch) against the same images rendered one by
+             one; the served workload (Poisson arrivals into the server
+             kernel) with p50/p99 latency, against sequential per-level
+             renders of the same requests
   cpu_baseline  the CPU oracle rendering the same full image on the host
              cores; its image is compared with the GPU image bit for bit
 """
@@ -41,7 +46,81 @@ def parse():
     ap.add_argument("--r", type=int, default=None)
     ap.add_argument("--B", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=256,
+                    help="images of the batched workload (0: skip it)")
+    ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--serve-seconds", type=float, default=5.0,
+                    help="seconds of Poisson arrivals (200/s) for the served workload (0: skip it)")
     return ap.parse_args()
+
+
+def batched_leg(ctx, torch, ask, workloads, sp, count, steps):
+    """The batched workload in one persistent launch per step, and the same
+    images rendered one at a time (persistent, then per-level form)."""
+    import numpy as np
+    ims = workloads.batch_images(count=count)
+    prms = [workloads.batch_params(w.W) for w in ims]
+    sizes = [w.pixels for w in ims]
+    total = sum(sizes)
+    offs = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    out = torch.empty(total, dtype=torch.int32, device="cuda")
+    ptrs = [out.data_ptr() + 4 * int(o) for o in offs]
+    wins = [ask.window(w) for w in ims]
+    pers = [ask.params(p.g, p.r, p.B, "persistent") for p in prms]
+    st = ask.ask_dwell_batch(ctx, wins, pers, ptrs, sp, want_stats=True)
+    iters = st["iters_ring"] + st["iters_leaf"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ask.ask_dwell_batch(ctx, wins, pers, ptrs, sp)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    ask.ask_synchronize(ctx, sp)
+    ask.ask_enable_timing(ctx, True)
+    ask.ask_dwell_batch(ctx, wins, pers, ptrs, sp)
+    kms = ask.ask_last_kernel_ms(ctx)
+    ask.ask_enable_timing(ctx, False)
+    batch_img = out.clone()
+
+    def one_by_one(form):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for w, p, ptr in zip(wins, prms, ptrs):
+            ask.ask_dwell_subdiv(ctx, w, ask.params(p.g, p.r, p.B, form), ptr, sp)
+        torch.cuda.synchronize()
+        ask.ask_synchronize(ctx, sp)
+        return 1e3 * (time.perf_counter() - t)
+
+    seq_pers_ms = one_by_one("persistent")
+    same = bool(torch.equal(out, batch_img))
+    seq_lv_ms = one_by_one("levels")
+    same = same and bool(torch.equal(out, batch_img))
+    del out, batch_img
+    return {"workload": "batch-%d-boundary-images" % count, "images": count, "pixels": total,
+            "ms": round(ms, 3), "mpix_s": round(total / (ms * 1e-3) / 1e6, 1),
+            "kernel_ms": round(kms, 3), "dwell_iterations": iters,
+            "fp64_frac": round(FLOPS_PER_ITERATION * iters / (kms * 1e-3) / 1e12
+                               / PEAK_FP64_TFLOPS, 4),
+            "one_by_one_persistent_ms": round(seq_pers_ms, 3),
+            "one_by_one_levels_ms": round(seq_lv_ms, 3),
+            "speedup_vs_one_by_one_levels": round(seq_lv_ms / ms, 2),
+            "equals_one_by_one": same}
+
+
+def served_leg(ctx, ask, workloads, seconds):
+    """Poisson arrivals at 200/s into the server kernel, and the same requests
+    rendered back to back by the per-level form."""
+    from paper_2206_02255_amd import serve
+    sched = workloads.serving_requests(seconds=seconds)
+    res = serve.serve(ctx, sched, workloads.batch_params, slots=64)
+    res.pop("images")
+    seq_s = serve.sequential(ctx, [w for _, w in sched], workloads.batch_params, "levels")
+    res["sequential_levels_mpix_s"] = round(res["pixels"] / seq_s / 1e6, 1)
+    res["arrival_seconds"] = seconds
+    for k in ("offered_mpix_s", "achieved_mpix_s", "makespan_s", "latency_p50_ms",
+              "latency_p99_ms", "latency_max_ms"):
+        res[k] = round(res[k], 3)
+    return res
 
 
 def main():
@@ -151,6 +230,12 @@ def main():
         },
         "cpu_baseline": None,
     }
+
+    if args.batch_count > 0:
+        result["forms"]["batched"] = batched_leg(ctx, torch, ask, workloads, sp, args.batch_count,
+                                                 args.batch_steps)
+    if args.serve_seconds > 0:
+        result["forms"]["served"] = served_leg(ctx, ask, workloads, args.serve_seconds)
 
     if not args.no_cpu_baseline:
         import numpy as np

@@ -38,6 +38,10 @@ class ask_params(C.Structure):
     _fields_ = [("g", C.c_uint32), ("r", C.c_uint32), ("B", C.c_uint32), ("form", C.c_uint32)]
 
 
+class ask_server_cfg(C.Structure):
+    _fields_ = [("slots", C.c_uint32), ("waves_per_cu", C.c_uint32), ("pool_bytes", C.c_uint64)]
+
+
 class ask_stats(C.Structure):
     _fields_ = [("levels", C.c_uint32), ("overflow", C.c_uint32),
                 ("regions", C.c_uint64 * MAX_LEVELS), ("fills", C.c_uint64 * MAX_LEVELS),
@@ -73,6 +77,14 @@ SIGNATURES = {
     "ask_set_wait_limit": (C.c_int, [_P, C.c_double]),
     "ask_enable_timing": (C.c_int, [_P, C.c_int]),
     "ask_last_kernel_ms": (C.c_int, [_P, C.POINTER(C.c_float)]),
+    "ask_server_create": (C.c_int, [_P, C.POINTER(ask_server_cfg), C.POINTER(_P)]),
+    "ask_server_submit": (C.c_int, [_P, C.POINTER(ask_window), C.POINTER(ask_params), _P,
+                                    C.POINTER(C.c_uint64)]),
+    "ask_server_reap": (C.c_int, [_P, C.POINTER(C.c_uint64), C.POINTER(C.c_int32), C.c_uint32,
+                                  C.POINTER(C.c_uint32)]),
+    "ask_server_poll": (C.c_int, [_P, C.c_uint64, C.POINTER(C.c_int)]),
+    "ask_server_in_flight": (C.c_int, [_P, C.POINTER(C.c_uint32)]),
+    "ask_server_destroy": (C.c_int, [_P]),
 }
 
 
@@ -183,3 +195,67 @@ def ask_dwell_batch(ctx, wins, prms, d_outs, stream=0, want_stats=False):
     _check(lib.ask_dwell_batch(ctx, n, W, P, len(prms), O, _P(stream),
                                C.byref(st) if st is not None else None), ctx)
     return st.as_dict() if st is not None else None
+
+
+# Servers still running when the interpreter exits are stopped first, so
+# that no server kernel outlives the process's last HIP call.
+_live_servers = {}
+
+
+def ask_server_create(ctx, slots=64, waves_per_cu=0, pool_bytes=0):
+    cfg = ask_server_cfg(int(slots), int(waves_per_cu), int(pool_bytes))
+    h = _P()
+    _check(lib.ask_server_create(ctx, C.byref(cfg), C.byref(h)), ctx)
+    _live_servers[h.value] = ctx
+    return h
+
+
+def ask_server_submit(sv, win, prm, d_out):
+    """Ticket of the posted request, or None when the server is busy
+    (no free slot or pool memory right now)."""
+    t = C.c_uint64()
+    s = lib.ask_server_submit(sv, C.byref(win), C.byref(prm), _P(d_out), C.byref(t))
+    if s == EBUSY:
+        return None
+    _check(s, _live_servers.get(sv.value))
+    return t.value
+
+
+def ask_server_reap(sv, cap=256):
+    """[(ticket, status)] of requests finished since the last reap."""
+    T = (C.c_uint64 * cap)()
+    S = (C.c_int32 * cap)()
+    n = C.c_uint32()
+    _check(lib.ask_server_reap(sv, T, S, cap, C.byref(n)), _live_servers.get(sv.value))
+    return [(T[i], S[i]) for i in range(n.value)]
+
+
+def ask_server_poll(sv, ticket):
+    """(done, status) of one request."""
+    d = C.c_int()
+    s = lib.ask_server_poll(sv, int(ticket), C.byref(d))
+    if s == EINVAL:
+        _check(s, _live_servers.get(sv.value))
+    return bool(d.value), s
+
+
+def ask_server_in_flight(sv):
+    n = C.c_uint32()
+    _check(lib.ask_server_in_flight(sv, C.byref(n)))
+    return n.value
+
+
+def ask_server_destroy(sv):
+    ctx = _live_servers.pop(sv.value, None)
+    _check(lib.ask_server_destroy(sv), ctx)
+
+
+def _stop_servers():
+    for h in list(_live_servers):
+        lib.ask_server_destroy(_P(h))
+        _live_servers.pop(h, None)
+
+
+import atexit  # noqa: E402
+
+atexit.register(_stop_servers)
