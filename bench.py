@@ -36,6 +36,11 @@ PEAK_FP64_TFLOPS = 78.6      # MI355X vector FP64, FMA counted as 2 flops
 FLOPS_PER_ITERATION = 8      # 3 multiplies + 5 adds of z <- z^2 + c and |z|^2
 
 
+def log(msg):
+    """Progress on stderr (the JSON result is the only stdout line)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -49,7 +54,7 @@ def parse():
     ap.add_argument("--batch-count", type=int, default=256,
                     help="images of the batched workload (0: skip it)")
     ap.add_argument("--batch-steps", type=int, default=3)
-    ap.add_argument("--serve-seconds", type=float, default=5.0,
+    ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="seconds of Poisson arrivals (200/s) for the served workload (0: skip it)")
     return ap.parse_args()
 
@@ -67,13 +72,15 @@ def batched_leg(ctx, torch, ask, workloads, sp, count, steps):
     ptrs = [out.data_ptr() + 4 * int(o) for o in offs]
     wins = [ask.window(w) for w in ims]
     pers = [ask.params(p.g, p.r, p.B, "persistent") for p in prms]
+    log("batched: %d images, %.2f Gpix; counting pass" % (count, total / 1e9))
     st = ask.ask_dwell_batch(ctx, wins, pers, ptrs, sp, want_stats=True)
     iters = st["iters_ring"] + st["iters_leaf"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for k in range(steps):
         ask.ask_dwell_batch(ctx, wins, pers, ptrs, sp)
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        log("batched: step %d of %d done" % (k + 1, steps))
     ms = 1e3 * (time.perf_counter() - t0) / steps
     ask.ask_synchronize(ctx, sp)
     ask.ask_enable_timing(ctx, True)
@@ -92,8 +99,10 @@ def batched_leg(ctx, torch, ask, workloads, sp, count, steps):
         return 1e3 * (time.perf_counter() - t)
 
     seq_pers_ms = one_by_one("persistent")
+    log("batched: one by one (persistent) done")
     same = bool(torch.equal(out, batch_img))
     seq_lv_ms = one_by_one("levels")
+    log("batched: one by one (levels) done")
     same = same and bool(torch.equal(out, batch_img))
     del out, batch_img
     return {"workload": "batch-%d-boundary-images" % count, "images": count, "pixels": total,
@@ -112,9 +121,12 @@ def served_leg(ctx, ask, workloads, seconds):
     rendered back to back by the per-level form."""
     from paper_2206_02255_amd import serve
     sched = workloads.serving_requests(seconds=seconds)
-    res = serve.serve(ctx, sched, workloads.batch_params, slots=64)
+    params_of = lambda w: workloads.batch_params(w.W)  # noqa: E731
+    log("served: %d requests over %.1f s" % (len(sched), seconds))
+    res = serve.serve(ctx, sched, params_of, slots=64, log=log)
     res.pop("images")
-    seq_s = serve.sequential(ctx, [w for _, w in sched], workloads.batch_params, "levels")
+    log("served: done; sequential per-level renders of the same requests")
+    seq_s = serve.sequential(ctx, [w for _, w in sched], params_of, "levels")
     res["sequential_levels_mpix_s"] = round(res["pixels"] / seq_s / 1e6, 1)
     res["arrival_seconds"] = seconds
     for k in ("offered_mpix_s", "achieved_mpix_s", "makespan_s", "latency_p50_ms",
@@ -154,6 +166,7 @@ def main():
     st = ask.ask_dwell_subdiv(ctx, win, prm, out.data_ptr(), sp, want_stats=True)
     iters = st["iters_ring"] + st["iters_leaf"]
 
+    log("main: %s, form %s, (g, r, B) = (%d, %d, %d)" % (w, form, g, r, B))
     for _ in range(args.warmup):
         render()
     ask.ask_synchronize(ctx, sp)
@@ -231,6 +244,7 @@ def main():
         "cpu_baseline": None,
     }
 
+    log("main: done (%.3f ms per step)" % ms_step)
     if args.batch_count > 0:
         result["forms"]["batched"] = batched_leg(ctx, torch, ask, workloads, sp, args.batch_count,
                                                  args.batch_steps)
@@ -240,6 +254,7 @@ def main():
     if not args.no_cpu_baseline:
         import numpy as np
         from oracle import askref
+        log("cpu baseline: the oracle on the full image")
         threads = os.cpu_count() or 1
         t0 = time.perf_counter()
         ref_img, _ = askref.subdiv(w, g, r, B, threads=threads)

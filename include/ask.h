@@ -201,8 +201,8 @@ ask_status ask_set_wait_limit(ask_ctx *ctx, double seconds);
  * ask_dwell_subdiv gives for the same window and parameters, bit for bit.
  *
  * Admission is by device memory: each request reserves, in the server's
- * pool, the worst-case size of its region queue and ring records (the
- * bounds ask_dwell_subdiv sizes its queue by); a request that does not fit,
+ * pool, the worst-case size of its region queue (the bound
+ * ask_dwell_subdiv sizes its queue by); a request that does not fit,
  * or finds every slot taken, is refused with ASK_EBUSY and can be posted
  * again once earlier requests have finished.
  *
@@ -218,7 +218,7 @@ typedef struct ask_server_cfg {
                               0: all but one 4-wave workgroup of the
                               kernel's occupancy */
     uint64_t pool_bytes;   /* device memory for the requests' region queues
-                              and ring records (0: 256 MiB) */
+                              (0: 256 MiB) */
 } ask_server_cfg;
 
 /* Start a server on ctx's device. *out receives it, or NULL on error. */

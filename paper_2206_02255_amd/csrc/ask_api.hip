@@ -31,8 +31,6 @@ struct ask_ctx {
     size_t lvq_cap = 0;                   // entries per table
     Region *queue = nullptr;              // persistent queue
     size_t queue_cap = 0;
-    RingRec *recs = nullptr;              // persistent form: segmented ring records
-    size_t rec_cap = 0;
     uint32_t epoch = 0;                   // 24-bit launch counter for queue tags
     double wait_limit_s = 10.0;           // persistent kernel: longest wait of one wave
     double clock_hz = 1e8;                // rate of the device's constant clock
@@ -141,46 +139,29 @@ uint64_t level_bound(uint64_t pixels, uint32_t g, uint32_t r, uint32_t lv) {
     return b >= (double)pixels ? pixels : (uint64_t)b;
 }
 
-// Worst-case work memory of a set of images (persistent form unless noted).
+// Worst-case queue memory of a set of images.
 struct Bounds {
     std::vector<uint64_t> level = std::vector<uint64_t>(kMaxLevels, 0);  // regions per level
-    uint64_t bands = 0;  // leaf bands
-    uint64_t segs = 0;   // extra ring-segment entries
-    uint64_t recs = 0;   // ring records
-    // Queue entries: bands and segments, and per level the regions and at
-    // most one last (short) band each.
-    uint64_t queue_entries() const {
-        uint64_t t = bands + segs;
+    uint64_t pixels = 0;
+    uint64_t regions() const {
+        uint64_t t = 0;
         for (uint64_t v : level)
-            t += 2 * v;
+            t += v;
         return t;
     }
+    // Queue entries when leaves are queued as bands of `band` pixels: the
+    // regions, and the bands, of which every one but a leaf's last has at
+    // least band / 2 pixels.
+    uint64_t queue_entries(uint32_t band) const { return pixels / (band / 2) + 2 * regions(); }
 };
 
 // Add one image's bounds to b; returns its level count.
 uint32_t add_bounds(const Image &im, Bounds &b) {
     const uint32_t lv_i = level_count(im.W, im.H, im.g, im.r, im.B);
     const uint64_t pixels = (uint64_t)im.W * im.H;
-    // Largest piece of each level (sw x sh), for the ring segments: a
-    // segmented ring has more than kSegPx pixels, so at most
-    // pixels / (kSegPx + 1) regions of a level have one, and their extra
-    // segment entries (ceil(ring / kSegPx) - 1 each) number at most
-    // pixels / kSegPx, the rings of a level being disjoint.
-    uint64_t sw = (im.W + im.g - 1) / im.g, sh = (im.H + im.g - 1) / im.g;
-    for (uint32_t lv = 0; lv < lv_i && lv < (uint32_t)kMaxLevels; ++lv) {
-        const uint64_t c = level_bound(pixels, im.g, im.r, lv);
-        b.level[lv] += c;
-        const uint64_t ring = (sw == 1 || sh == 1) ? sw * sh : 2 * (sw + sh) - 4;
-        if (ring > kSegPx) {
-            b.recs += std::min<uint64_t>(c, pixels / (kSegPx + 1));
-            b.segs += std::min<uint64_t>(pixels / kSegPx, c * ((ring + kSegPx - 1) / kSegPx - 1));
-        }
-        sw = (sw + im.r - 1) / im.r;
-        sh = (sh + im.r - 1) / im.r;
-    }
-    // Leaf bands: every band but a leaf's last holds at least kLeafTask / 2
-    // pixels.
-    b.bands += pixels / (kLeafTask / 2);
+    for (uint32_t lv = 0; lv < lv_i && lv < (uint32_t)kMaxLevels; ++lv)
+        b.level[lv] += level_bound(pixels, im.g, im.r, lv);
+    b.pixels += pixels;
     return lv_i;
 }
 
@@ -405,7 +386,6 @@ ask_status ask_destroy(ask_ctx *ctx) {
         (void)hipFree(ctx->lvq[0]);
         (void)hipFree(ctx->lvq[1]);
         (void)hipFree(ctx->queue);
-        (void)hipFree(ctx->recs);
         if (ctx->ev[0])
             (void)hipEventDestroy(ctx->ev[0]);
         if (ctx->ev[1])
@@ -464,19 +444,15 @@ ask_status render(ask_ctx *ctx, const Image *ims, uint32_t n, uint32_t form, hip
     if (nseeds > 0x7fffffffull)
         return fail(ctx, ASK_EINVAL, "too many level-0 regions%s", nullptr);
     const std::vector<uint64_t> &bound = b.level;
-    const uint64_t recs = b.recs;
     uint64_t widest = 0;
     for (uint32_t lv = 0; lv < levels; ++lv)
         widest = std::max(widest, bound[lv]);
-    const uint64_t total = b.queue_entries();
-    const uint64_t need = form == ASK_FORM_PERSISTENT ? total : widest;
+    const uint64_t need = form == ASK_FORM_PERSISTENT ? b.queue_entries(kLeafTask) : widest;
     const uint64_t want = std::min<uint64_t>(need, kQueueBudget);
-    const bool may_overflow = need > want || recs > kQueueBudget;
+    const bool may_overflow = need > want;
     ask_status st;
     if (form == ASK_FORM_PERSISTENT) {
         st = grow(ctx, &ctx->queue, &ctx->queue_cap, want, true);
-        if (st == ASK_OK && recs > 0)
-            st = grow(ctx, &ctx->recs, &ctx->rec_cap, std::min<uint64_t>(recs, kQueueBudget), false);
     } else {
         size_t cap0 = ctx->lvq_cap;
         st = grow(ctx, &ctx->lvq[0], &cap0, want, false);
@@ -556,8 +532,8 @@ ask_status render(ask_ctx *ctx, const Image *ims, uint32_t n, uint32_t form, hip
         }
         a.queue = ctx->queue;
         a.cap = (uint32_t)std::min<size_t>(ctx->queue_cap, 0xffffffffu - 65536u);
-        a.recs = ctx->recs;
-        a.rec_cap = (uint32_t)std::min<size_t>(ctx->rec_cap, 0xffffffffu);
+        a.leaf_band = kLeafTask;
+        a.leaf_min = kLeafTask;
         a.epoch = ctx->epoch;
         a.wait_ticks = (uint64_t)(ctx->wait_limit_s * ctx->clock_hz);
         e = launch_seed_queue(a, (uint32_t)nseeds, s);
@@ -749,17 +725,16 @@ struct ask_server {
     ServerSlot *slots = nullptr;
     ServerCtl *ctl = nullptr;
     Region *queue = nullptr;
-    RingRec *recs = nullptr;
-    uint64_t queue_entries = 0, rec_entries = 0;
+    uint64_t queue_entries = 0;
     ServerMailbox *mb = nullptr;      // host address of the pinned mailbox
     ServerMailbox *mb_dev = nullptr;  // its device address
-    PoolAlloc qpool, rpool;
+    PoolAlloc qpool;
     struct Flight {
         bool busy = false;
         bool quarantined = false;  // finished with an error: slot and memory never reused
         uint64_t ticket = 0;
         uint32_t gen = 0;
-        uint64_t qoff = 0, qlen = 0, roff = 0, rlen = 0;
+        uint64_t qoff = 0, qlen = 0;
     } flight[kMaxSlots];
     uint32_t next_gen = 1;
     uint64_t next_ticket = 1;
@@ -773,9 +748,11 @@ namespace {
 
 hipError_t server_launch(ask_server *sv) {
     ask_ctx *ctx = sv->ctx;
-    // No server kernel runs now: reset the device words, and ring again only
-    // the doorbells of requests posted and not finished.
+    // No server kernel runs now: reset the device words and slots, and ring
+    // again only the doorbells of requests posted and not finished.
     hipError_t e = hipMemsetAsync(sv->ctl, 0, sizeof(ServerCtl), sv->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(sv->slots, 0, sizeof(ServerSlot) * sv->nslots, sv->stream);
     if (e != hipSuccess)
         return e;
     __atomic_store_n(&sv->mb->stop, 0u, __ATOMIC_RELAXED);
@@ -788,7 +765,6 @@ hipError_t server_launch(ask_server *sv) {
     a.ctl = sv->ctl;
     a.nslots = sv->nslots;
     a.queue = sv->queue;
-    a.recs = sv->recs;
     a.mb = sv->mb_dev;
     a.wait_ticks = (uint64_t)(ctx->wait_limit_s * ctx->clock_hz);
     a.poll_ticks = std::max<uint64_t>(1, (uint64_t)(2e-6 * ctx->clock_hz));
@@ -810,7 +786,6 @@ void server_reap(ask_server *sv) {
         --sv->in_flight;
         if (status == ASK_OK) {
             sv->qpool.release(f.qoff, f.qlen);
-            sv->rpool.release(f.roff, f.rlen);
         } else {
             f.quarantined = true;
             sv->failed[f.ticket] = status;
@@ -873,10 +848,7 @@ ask_status ask_server_create(ask_ctx *ctx, const ask_server_cfg *cfg, ask_server
     sv->ctx = ctx;
     sv->nslots = cfg->slots;
     sv->blocks = (uint32_t)ctx->cus * per_cu;
-    // Pool: 1/8 for ring records (32 B), the rest for queue entries (16 B).
-    sv->rec_entries = std::min<uint64_t>(pool / 8 / sizeof(RingRec), 0xffffffffull);
-    sv->queue_entries = std::min<uint64_t>((pool - sv->rec_entries * sizeof(RingRec)) / sizeof(Region),
-                                           0xffffffffull);
+    sv->queue_entries = std::min<uint64_t>(pool / sizeof(Region), 0xffffffffull);
     hipError_t e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
     if (e == hipSuccess)
         e = hipMalloc((void **)&sv->slots, sizeof(ServerSlot) * sv->nslots);
@@ -884,8 +856,6 @@ ask_status ask_server_create(ask_ctx *ctx, const ask_server_cfg *cfg, ask_server
         e = hipMalloc((void **)&sv->ctl, sizeof(ServerCtl));
     if (e == hipSuccess)
         e = hipMalloc((void **)&sv->queue, sizeof(Region) * sv->queue_entries);
-    if (e == hipSuccess)
-        e = hipMalloc((void **)&sv->recs, sizeof(RingRec) * sv->rec_entries);
     if (e == hipSuccess)
         e = hipMemset(sv->queue, 0, sizeof(Region) * sv->queue_entries);  // no entry carries a generation
     if (e == hipSuccess)
@@ -895,7 +865,6 @@ ask_status ask_server_create(ask_ctx *ctx, const ask_server_cfg *cfg, ask_server
     if (e == hipSuccess) {
         memset(sv->mb, 0, sizeof(ServerMailbox));
         sv->qpool.reset(sv->queue_entries);
-        sv->rpool.reset(sv->rec_entries);
         e = server_launch(sv);
     }
     if (e != hipSuccess) {
@@ -905,8 +874,7 @@ ask_status ask_server_create(ask_ctx *ctx, const ask_server_cfg *cfg, ask_server
         (void)hipFree(sv->slots);
         (void)hipFree(sv->ctl);
         (void)hipFree(sv->queue);
-        (void)hipFree(sv->recs);
-        (void)hipHostFree(sv->mb);
+            (void)hipHostFree(sv->mb);
         if (sv->stream)
             (void)hipStreamDestroy(sv->stream);
         delete sv;
@@ -928,8 +896,8 @@ ask_status ask_server_submit(ask_server *sv, const ask_window *win, const ask_pa
     Bounds b;
     if (add_bounds(im, b) > (uint32_t)kMaxLevels - 1)
         return fail(ctx, ASK_EINVAL, "too many levels%s", nullptr);
-    const uint64_t qlen = b.queue_entries(), rlen = b.recs;
-    if (qlen > sv->queue_entries || rlen > sv->rec_entries)
+    const uint64_t qlen = b.queue_entries(kLeafTask);
+    if (qlen > sv->queue_entries)
         return fail(ctx, ASK_ENOMEM, "the request's worst case exceeds the server pool%s", nullptr);
     DeviceGuard guard(ctx->device);
     server_reap(sv);
@@ -955,20 +923,14 @@ ask_status ask_server_submit(ask_server *sv, const ask_window *win, const ask_pa
         ++k;
     if (k == sv->nslots)
         return fail(ctx, ASK_EBUSY, "no free request slot%s", nullptr);
-    uint64_t qoff = 0, roff = 0;
+    uint64_t qoff = 0;
     if (!sv->qpool.alloc(qlen, &qoff))
         return fail(ctx, ASK_EBUSY, "not enough free queue memory%s", nullptr);
-    if (rlen && !sv->rpool.alloc(rlen, &roff)) {
-        sv->qpool.release(qoff, qlen);
-        return fail(ctx, ASK_EBUSY, "not enough free record memory%s", nullptr);
-    }
     const uint32_t gen = sv->next_gen++;
     ServerPost &p = sv->mb->post[k];
     p.im = im;
     p.qoff = (uint32_t)qoff;
     p.qcap = (uint32_t)qlen;
-    p.roff = (uint32_t)roff;
-    p.rcap = (uint32_t)rlen;
     __atomic_store_n(&sv->mb->doorbell[k], gen, __ATOMIC_RELEASE);
     ask_server::Flight &f = sv->flight[k];
     f.busy = true;
@@ -976,8 +938,6 @@ ask_status ask_server_submit(ask_server *sv, const ask_window *win, const ask_pa
     f.gen = gen;
     f.qoff = qoff;
     f.qlen = qlen;
-    f.roff = roff;
-    f.rlen = rlen;
     ++sv->in_flight;
     *ticket = f.ticket;
     return ASK_OK;
@@ -1043,7 +1003,6 @@ ask_status ask_server_destroy(ask_server *sv) {
     (void)hipFree(sv->slots);
     (void)hipFree(sv->ctl);
     (void)hipFree(sv->queue);
-    (void)hipFree(sv->recs);
     (void)hipHostFree(sv->mb);
     (void)hipStreamDestroy(sv->stream);
     ctx->server = nullptr;

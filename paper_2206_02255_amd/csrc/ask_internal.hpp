@@ -29,28 +29,14 @@ struct Region {
                     // tag is stored last, with release order, and marks the entry valid
 };
 
-// Entry kinds: a region to scan (border query, then fill, leaf or split), a
-// band of a leaf whose pixels are all computed, or one segment of a long
-// ring scanned by several waves (persistent form). A segment entry holds
-// {record index, segment | segments << 16, 0, tag}.
-enum Kind : uint32_t { kScan = 0, kLeaf = 1, kSeg = 2 };
+// Entry kinds: a region to scan (border query, then fill, leaf or split), or
+// a band of a leaf whose pixels are all computed.
+enum Kind : uint32_t { kScan = 0, kLeaf = 1 };
 
-// Pixels per queued leaf task (persistent form).
+// Leaf bands of the queue forms: leaves above kLeafTask pixels are queued as
+// bands of about kLeafTask pixels, each computed by the wave that takes it,
+// so that no wave holds a whole large leaf while others idle.
 constexpr uint32_t kLeafTask = 1024;
-
-// Persistent form: a ring of more than kSegPx pixels is scanned as
-// ceil(ring / kSegPx) segments, each a task of its own.
-constexpr uint32_t kSegPx = 256;
-
-// Shared state of a ring scanned in segments. `v` is the reference dwell
-// (kNoValue until the first segment fixes it), `left` the segments not yet
-// finished, `mixed` nonzero once any segment has found a pixel whose dwell
-// differs from v. The segment that brings `left` to zero decides the region.
-constexpr uint32_t kNoValue = 0xffffffffu;
-struct RingRec {
-    uint32_t img, xy, wh, level;
-    uint32_t v, left, mixed, pad;
-};
 
 __host__ __device__ inline uint32_t pack_xy(uint32_t x, uint32_t y) { return x | (y << 16); }
 __host__ __device__ inline uint32_t pack_wh(uint32_t w, uint32_t h) { return (w - 1) | ((h - 1) << 16); }
@@ -67,17 +53,20 @@ struct DevStats {
     uint32_t overflow;
 };
 
-// Control words in device memory.
+// Control words in device memory. The counters that every wave updates
+// (head, tail, pending) sit on cache lines of their own (128 bytes apart):
+// atomics and polls of one line are served one at a time, and sharing a line
+// made them the bottleneck of renders with many small regions.
 enum Ctrl : uint32_t {
     kCount = 0,                   // [kCount + lv]: regions written for level lv
     kClaim = kCount + kMaxLevels, // [kClaim + lv]: next region a wave takes at level lv
-    kHead = kClaim + kMaxLevels,  // persistent queue: next slot to take
-    kTail,                        // persistent queue: next slot to fill
-    kPending,                     // persistent queue: regions taken or queued, not finished
-    kOverflow,                    // this render: a queue ran out of room
-    kRecs,                        // persistent queue: ring records handed out
-    kSticky = 255,                // error bits of all renders since the last check
-    kCtrlWords = 256
+    kHead = 256,                  // persistent queue: next slot to take
+    kTail = 288,                  // persistent queue: next slot to fill
+    kPending = 320,               // persistent queue: entries queued or taken, not finished
+    kOverflow = 352,              // this render: a queue ran out of room
+    kRefs = 384,                  // serving: waves holding a reference to the slot
+    kSticky = 511,                // error bits of all renders since the last check
+    kCtrlWords = 512
 };
 
 enum ErrBits : uint32_t { kErrOverflow = 1, kErrTimeout = 2 };
@@ -91,10 +80,11 @@ struct SubdivArgs {
     uint32_t level;             // level kernels: the level being processed
     const Region *in;           // level kernels: regions of this level
     Region *out;                // level kernels: regions of the next level
-    Region *queue;              // persistent kernel: the queue
+    Region *queue;              // persistent kernel: the region queue
     uint32_t cap;               // capacity (entries) of out / queue
-    RingRec *recs;              // persistent kernel: records of segmented rings
-    uint32_t rec_cap;
+    uint32_t leaf_band;         // queue forms: pixels per leaf band
+    uint32_t leaf_min;          // queue forms: leaves above this many pixels are queued as
+                                // bands, smaller ones computed by the wave that decides them
     uint32_t epoch;
     uint64_t wait_ticks;        // persistent kernel: longest wait, constant-clock ticks
     uint32_t *ctrl;
@@ -109,13 +99,14 @@ constexpr uint32_t kMaxSlots = 64;
 // Slot state word: gen << 8 | kind. gen (24 bits, never 0 for a request) is
 // the request's generation; it tags the request's queue entries, so entries
 // left in reused pool memory by earlier requests are never taken for its own.
-enum SlotKind : uint32_t { kSlotFree = 0, kSlotAdmitting = 1, kSlotActive = 2 };
+// A finished request's slot stays kSlotDone until the last wave holding a
+// reference to it has left, and only then becomes free for the next request.
+enum SlotKind : uint32_t { kSlotFree = 0, kSlotAdmitting = 1, kSlotActive = 2, kSlotDone = 3 };
 
 // What the host posts for a request (pinned host memory).
 struct ServerPost {
     Image im;
     uint32_t qoff, qcap;  // the request's region queue: entries [qoff, qoff + qcap) of the pool
-    uint32_t roff, rcap;  // its ring records: [roff, roff + rcap) of the record pool
 };
 
 // What the device reports when a request has finished (pinned host memory);
@@ -135,8 +126,7 @@ struct ServerMailbox {
 
 // A slot's request, in device memory.
 struct ServerSlot {
-    uint32_t ctrl[kCtrlWords];   // the request's tail, pending, record and error words
-    unsigned long long claim;    // gen << 32 | next queue index to take
+    uint32_t ctrl[kCtrlWords];   // the request's head, tail, pending, error and reference words
     ServerPost post;             // copy of the request's post
 };
 
@@ -153,7 +143,6 @@ struct ServerArgs {
     ServerCtl *ctl;
     uint32_t nslots;
     Region *queue;        // entry pool shared by the requests' queues
-    RingRec *recs;        // record pool
     ServerMailbox *mb;    // pinned host memory
     uint64_t wait_ticks;  // longest wait for a claimed entry
     uint64_t poll_ticks;  // mailbox poll interval

@@ -133,22 +133,29 @@ __device__ __forceinline__ unsigned long long clock_now() {
     return ((unsigned long long)uniform((uint32_t)(t >> 32)) << 32) | uniform((uint32_t)t);
 }
 
-// One atomic per wave: every lane issues it and only the first active lane
-// contributes (a select, not a branch); every lane gets the old value.
+// One atomic per wave, issued by the first active lane alone; every lane
+// gets the old value through readfirstlane (which reads that same lane, also
+// if the optimiser moves it into the branch).
 __device__ __forceinline__ uint32_t wave_add(uint32_t *p, uint32_t v) {
-    return uniform(atomicAdd(p, first_lane() ? v : 0u));
+    uint32_t old = 0;
+    if (first_lane())
+        old = atomicAdd(p, v);
+    return uniform(old);
 }
 
 __device__ __forceinline__ void wave_add64(unsigned long long *p, unsigned long long v) {
-    atomicAdd(p, first_lane() ? v : 0ull);
+    if (first_lane())
+        atomicAdd(p, v);
 }
 
 __device__ __forceinline__ void wave_or(uint32_t *p, uint32_t v) {
-    atomicOr(p, first_lane() ? v : 0u);
+    if (first_lane())
+        atomicOr(p, v);
 }
 
 __device__ __forceinline__ void wave_max(uint32_t *p, uint32_t v) {
-    atomicMax(p, first_lane() ? v : 0u);
+    if (first_lane())
+        atomicMax(p, v);
 }
 
 // ---------------------------------------------------------------------------
@@ -188,58 +195,32 @@ __global__ __launch_bounds__(kBlock) void exhaustive_kernel(Image im) {
 // pixel_of(i, px, py) names pixel i of the stream (false: no pixel there);
 // done(px, py, dwell) is called by the lane that finished a pixel.
 //
-// Border streams (an active border policy) also decide uniformity, and stop
-// as soon as the border is known to be mixed: once some pixel has finished
-// with dwell v (the policy fixes v: this wave's first, or the first of any
-// segment of the ring), the border is mixed if another pixel finishes with a
-// different dwell, if a pixel still running has already done v iterations
-// (its dwell is larger than v), or if the policy reports that another
-// segment found it mixed. The decision is the same as after the whole
-// border; only the remaining iterations are saved. The return value is then
-// false; for a border whose every pixel finished with v it is true.
+// Border streams (WaveBorder) also decide uniformity, and stop as soon as the
+// border is known to be mixed: once some pixel has finished with dwell v (the
+// least dwell of the first round in which any pixel finished), the border is
+// mixed if another pixel finishes with a different dwell, or if a pixel still
+// running has already done v iterations (its dwell is larger than v). The
+// decision is the same as after the whole border; only the remaining
+// iterations are saved. The return value is then false; for a border whose
+// every pixel finished with v it is true.
 // `partial` receives, per lane, the iterations of a pixel left unfinished by
 // an early stop (work done, for the counters).
 // ---------------------------------------------------------------------------
 constexpr uint32_t kRoundBlocks = 2;
 
-// Border policies of dwell_stream. A leaf stream has none; a ring scanned by
-// one wave takes the first finished dwell as its reference; a ring segment
-// shares the reference and the "mixed" verdict with the other segments of
-// its ring through the ring's record.
+// Border policies of dwell_stream: a leaf stream has none; a ring stream
+// decides uniformity against its first finished dwell.
 struct NoBorder {
     static constexpr bool kActive = false;
-    __device__ uint32_t settle(uint32_t v) const { return v; }
-    __device__ bool stopped() const { return false; }
 };
 
 struct WaveBorder {
     static constexpr bool kActive = true;
-    __device__ uint32_t settle(uint32_t v) const { return v; }
-    __device__ bool stopped() const { return false; }
-};
-
-struct SharedBorder {
-    static constexpr bool kActive = true;
-    RingRec *rec;
-    // The first segment to finish a pixel publishes that dwell; every
-    // segment compares against the published value.
-    __device__ uint32_t settle(uint32_t v) const {
-        uint32_t old = kNoValue;
-        if (first_lane())
-            old = atomicCAS(&rec->v, kNoValue, v);
-        old = uniform(old);
-        return old == kNoValue ? v : old;
-    }
-    __device__ bool stopped() const {
-        return uniform(__hip_atomic_load(&rec->mixed, __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT)) != 0;
-    }
 };
 
 template <class Border, class PixelOf, class Done>
 __device__ __forceinline__ bool dwell_stream(const Image &im, uint32_t n, PixelOf pixel_of,
-                                             Done done, const Border &border, uint32_t &v,
-                                             uint32_t &partial) {
+                                             Done done, Border, uint32_t &v, uint32_t &partial) {
     const uint32_t D = im.D;
     uint32_t next = 0;  // first stream index no lane has taken yet (uniform)
     bool have = false, special = false, vset = false;
@@ -247,8 +228,11 @@ __device__ __forceinline__ bool dwell_stream(const Image &im, uint32_t n, PixelO
     double cr = 0.0, ci = 0.0, zr = 0.0, zi = 0.0, zr2 = 0.0, zi2 = 0.0;
     partial = 0;
     for (;;) {
-        const unsigned long long idle = __ballot(!have);
-        if (idle && next < n) {
+        // Idle lanes take the next stream positions; a position that names no
+        // pixel is passed over, so this repeats until no lane is idle or the
+        // stream is exhausted.
+        unsigned long long idle = __ballot(!have);
+        while (idle && next < n) {
             if (!have) {
                 const uint32_t j = next + lane_rank(idle);
                 if (j < n && pixel_of(j, px, py)) {
@@ -260,12 +244,10 @@ __device__ __forceinline__ bool dwell_stream(const Image &im, uint32_t n, PixelO
                 }
             }
             next = min(n, next + (uint32_t)__popcll(idle));
+            idle = __ballot(!have);
         }
-        if (__ballot(have) == 0) {
-            if (next >= n)
-                break;
-            continue;  // this batch named no pixel (skipped positions): take the next
-        }
+        if (__ballot(have) == 0)
+            break;
         uint32_t dw = 0;
         bool fin = false;
         if (have) {
@@ -320,10 +302,10 @@ __device__ __forceinline__ bool dwell_stream(const Image &im, uint32_t n, PixelO
         }
         if (Border::kActive) {
             if (!vset && __ballot(fin)) {
-                v = border.settle(uniform(wave_min(fin ? dw : 0xffffffffu)));
+                v = uniform(wave_min(fin ? dw : 0xffffffffu));
                 vset = true;
             }
-            if (vset && (__ballot((fin && dw != v) || (have && kbase >= v)) || border.stopped())) {
+            if (vset && __ballot((fin && dw != v) || (have && kbase >= v))) {
                 partial = have ? kbase : 0u;
                 return false;
             }
@@ -416,13 +398,16 @@ __device__ __forceinline__ Image image_of(const SubdivArgs &a, uint32_t img) {
 }
 
 // Append `count` entries (entry_of(j, e) fills e's img, xy and wh, or
-// returns false for an empty one) to the next level's table (per-level form)
-// or to the queue (persistent form) with the given kind and level, using one
-// atomic add per wave and per 64 entries: a ballot of the non-empty entries
-// and their rank give every entry its slot (Sec. 5.3.1, compact insertion).
+// returns false for an empty one) to table q, whose next free slot is *tail
+// and whose capacity is cap: the next level's table (per-level form) or a
+// queue (persistent forms), with the given kind and level, using one atomic
+// add per wave and per 64 entries: a ballot of the non-empty entries and
+// their rank give every entry its slot (Sec. 5.3.1, compact insertion).
+// Queue entries are counted as pending and published by their tag.
 template <bool kQueue, class EntryOf>
-__device__ void emit_entries(const SubdivArgs &a, uint32_t count, uint32_t kind, uint32_t level,
-                             uint32_t lane, EntryOf entry_of) {
+__device__ void emit_entries(const SubdivArgs &a, Region *q, uint32_t *tail, uint32_t cap,
+                             uint32_t count, uint32_t kind, uint32_t level, uint32_t lane,
+                             EntryOf entry_of) {
     const uint32_t tag = (a.epoch << 8) | (kind << 6) | level;
     for (uint32_t base = 0; base < count; base += kWave) {
         const uint32_t j = base + lane;
@@ -432,8 +417,8 @@ __device__ void emit_entries(const SubdivArgs &a, uint32_t count, uint32_t kind,
         const uint32_t n = (uint32_t)__popcll(mask);
         if (n == 0)
             continue;
-        const uint32_t slot0 = wave_add(kQueue ? &a.ctrl[kTail] : &a.ctrl[kCount + level], n);
-        const bool fits = (uint64_t)slot0 + n <= a.cap;
+        const uint32_t slot0 = wave_add(tail, n);
+        const bool fits = (uint64_t)slot0 + n <= cap;
         if (fits) {
             if (kQueue)
                 wave_add(&a.ctrl[kPending], n);
@@ -442,15 +427,14 @@ __device__ void emit_entries(const SubdivArgs &a, uint32_t count, uint32_t kind,
             wave_or(&a.ctrl[kSticky], kErrOverflow);
         }
         if (ok && fits) {
-            const uint32_t slot = slot0 + lane_rank(mask);
+            Region *d = q + slot0 + lane_rank(mask);
             if (kQueue) {
-                Region *q = a.queue + slot;
-                q->img = e.img;
-                q->xy = e.xy;
-                q->wh = e.wh;
-                __hip_atomic_store(&q->tag, tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                d->img = e.img;
+                d->xy = e.xy;
+                d->wh = e.wh;
+                __hip_atomic_store(&d->tag, tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             } else {
-                a.out[slot] = e;
+                *d = e;
             }
         }
     }
@@ -461,7 +445,9 @@ __device__ void emit_entries(const SubdivArgs &a, uint32_t count, uint32_t kind,
 template <bool kQueue>
 __device__ void split_region(const SubdivArgs &a, uint32_t img, uint32_t x, uint32_t y,
                              uint32_t w, uint32_t h, uint32_t r, uint32_t level, uint32_t lane) {
-    emit_entries<kQueue>(a, r * r, kScan, level + 1, lane, [&](uint32_t j, Region &e) {
+    Region *q = kQueue ? a.queue : a.out;
+    uint32_t *tail = kQueue ? &a.ctrl[kTail] : &a.ctrl[kCount + level + 1];
+    emit_entries<kQueue>(a, q, tail, a.cap, r * r, kScan, level + 1, lane, [&](uint32_t j, Region &e) {
         const uint32_t jx = j % r, jy = j / r;
         const uint32_t x0 = x + (uint32_t)(((uint64_t)jx * w) / r);
         const uint32_t x1 = x + (uint32_t)(((uint64_t)(jx + 1) * w) / r);
@@ -474,20 +460,20 @@ __device__ void split_region(const SubdivArgs &a, uint32_t img, uint32_t x, uint
     });
 }
 
-// Persistent form: the per-pixel work of a leaf becomes row bands of about
-// kLeafTask pixels, queued as leaf tasks that any wave can take, so that no
-// wave holds a whole leaf while the others idle.
+// Queue forms: the per-pixel work of a leaf becomes row bands of about
+// a.leaf_band pixels, queued as leaf entries that any wave can take.
 __device__ void queue_leaf_bands(const SubdivArgs &a, uint32_t img, uint32_t x, uint32_t y,
                                  uint32_t w, uint32_t h, uint32_t level, uint32_t lane) {
-    const uint32_t hb = max(1u, kLeafTask / w);
+    const uint32_t hb = max(1u, a.leaf_band / w);
     const uint32_t nb = (h + hb - 1) / hb;
-    emit_entries<true>(a, nb, kLeaf, level, lane, [&](uint32_t j, Region &e) {
-        const uint32_t y0 = y + j * hb;
-        e.img = img;
-        e.xy = pack_xy(x, y0);
-        e.wh = pack_wh(w, min(y + h, y0 + hb) - y0);
-        return true;
-    });
+    emit_entries<true>(a, a.queue, &a.ctrl[kTail], a.cap, nb, kLeaf, level, lane,
+                       [&](uint32_t j, Region &e) {
+                           const uint32_t y0 = y + j * hb;
+                           e.img = img;
+                           e.xy = pack_xy(x, y0);
+                           e.wh = pack_wh(w, min(y + h, y0 + hb) - y0);
+                           return true;
+                       });
 }
 
 // What follows the border query of a region (Sec. 4.2.1): fill T when the
@@ -510,7 +496,7 @@ __device__ void decide_region(const SubdivArgs &a, uint32_t img, const Image &im
     if (w <= im.B && h <= im.B) {
         if (st)
             wave_add64(&st->leaves[level], 1ull);
-        if (kQueue && w * h > kLeafTask) {
+        if (kQueue && w * h > a.leaf_min) {
             queue_leaf_bands(a, img, x, y, w, h, level, lane);
             return;
         }
@@ -529,84 +515,39 @@ __device__ void decide_region(const SubdivArgs &a, uint32_t img, const Image &im
         wave_add64(&st->splits[level], 1ull);
 }
 
-// Q over the ring pixels t = s, s + step, s + 2 step, ... (all of them for
-// s = 0, step = 1), leaving out the multiples of `skip` when skip > 0, taken
-// in a spread order: the first 64 are spaced evenly over the list, the next
-// 64 follow them, and so on. Returns whether every one finished with dwell
-// v; adds the iterations done to the counters.
-template <class Border>
+// Q over the whole ring, taken in a spread order: the first 64 pixels are
+// spaced evenly around the ring, the next 64 follow them, and so on, so that
+// a mixed ring is usually found mixed in the first round. Returns whether
+// every ring pixel finished with dwell v; adds the iterations done to the
+// counters.
 __device__ bool scan_ring(const SubdivArgs &a, const Image &im, uint32_t x, uint32_t y,
-                          uint32_t w, uint32_t h, uint32_t s, uint32_t step, uint32_t skip,
-                          const Border &border, uint32_t &v) {
+                          uint32_t w, uint32_t h, uint32_t &v) {
     const uint32_t nring = ring_size(w, h);
-    const uint32_t m = (nring - s + step - 1) / step;
-    const uint32_t q = (m + kWave - 1) / kWave;
+    const uint32_t q = (nring + kWave - 1) / kWave;
     unsigned long long it = 0;
     uint32_t partial = 0;
     const bool same = dwell_stream(
         im, q * kWave,
         [&](uint32_t j, uint32_t &px, uint32_t &py) {
-            const uint32_t i = (j % kWave) * q + j / kWave;
-            const uint32_t t = s + i * step;
-            if (i >= m || (skip && t % skip == 0))
+            const uint32_t t = (j % kWave) * q + j / kWave;
+            if (t >= nring)
                 return false;
             ring_pixel(x, y, w, h, t, px, py);
             return true;
         },
-        [&](uint32_t, uint32_t, uint32_t d) { it += d; }, border, v, partial);
+        [&](uint32_t, uint32_t, uint32_t d) { it += d; }, WaveBorder{}, v, partial);
     if (a.stats)
         wave_add64(&a.stats->iters_ring, wave_sum(it + partial));
     return same;
 }
 
-// Stride of the probe of a long ring: its pixels 0, p, 2p, ... (at most 64).
-__device__ __forceinline__ uint32_t probe_stride(uint32_t nring) {
-    return (nring + kWave - 1) / kWave;
-}
-
-// One segment of a segmented ring: scan its pixels, publish a mixed verdict,
-// and, as the ring's last segment to finish, decide the region.
-__device__ void scan_segment(const SubdivArgs &a, uint32_t rid, uint32_t seg, uint32_t nseg,
-                             uint32_t lane) {
-    RingRec *rec = a.recs + rid;
-    const uint32_t img = uniform(rec->img), xy = uniform(rec->xy), wh = uniform(rec->wh);
-    const uint32_t level = uniform(rec->level);
-    const Image im = image_of(a, img);
-    const uint32_t x = xy & 0xffffu, y = xy >> 16;
-    const uint32_t w = (wh & 0xffffu) + 1, h = (wh >> 16) + 1;
-    uint32_t v = 0;
-    if (!scan_ring(a, im, x, y, w, h, seg, nseg, probe_stride(ring_size(w, h)), SharedBorder{rec}, v))
-        __hip_atomic_store(&rec->mixed, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    // The count-down releases this wave's verdict and, for the last segment,
-    // acquires every other segment's.
-    uint32_t left = 0;
-    if (first_lane())
-        left = __hip_atomic_fetch_add(&rec->left, (uint32_t)-1, __ATOMIC_ACQ_REL,
-                                      __HIP_MEMORY_SCOPE_AGENT);
-    if (uniform(left) != 1u)
-        return;
-    const bool mixed = uniform(__hip_atomic_load(&rec->mixed, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT)) != 0;
-    const uint32_t vv = uniform(__hip_atomic_load(&rec->v, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT));
-    decide_region<true>(a, img, im, x, y, w, h, level, !mixed, vv, lane);
-}
-
 // One region, by one wave: border query Q, then fill T, leaf L or split S
-// (Sec. 4.2.1). In the persistent form a ring longer than kSegPx pixels is
-// first probed at 64 evenly spaced pixels; a mixed probe decides at once,
-// and a uniform one (a likely fill, with no children to wait for) cuts the
-// rest of the ring into segments: this wave scans the first, the others go
-// to the queue.
+// (Sec. 4.2.1).
 template <bool kQueue>
 __device__ void process_region(const SubdivArgs &a, const Region &R, uint32_t lane) {
     const uint32_t img = uniform(R.img), xy = uniform(R.xy), wh = uniform(R.wh);
     const uint32_t tag = uniform(R.tag);
     const uint32_t level = tag & 0x3fu, kind = (tag >> 6) & 0x3u;
-    if (kQueue && kind == kSeg) {
-        scan_segment(a, img, xy & 0xffffu, xy >> 16, lane);
-        return;
-    }
     const Image im = image_of(a, img);
     const uint32_t x = xy & 0xffffu, y = xy >> 16;
     const uint32_t w = (wh & 0xffffu) + 1, h = (wh >> 16) + 1;
@@ -616,34 +557,8 @@ __device__ void process_region(const SubdivArgs &a, const Region &R, uint32_t la
             wave_add64(&a.stats->iters_leaf, wave_sum(li));
         return;
     }
-    const uint32_t nring = ring_size(w, h);
     uint32_t v = 0;
-    if (kQueue && nring > kSegPx) {
-        const uint32_t p = probe_stride(nring);
-        if (!scan_ring(a, im, x, y, w, h, 0, p, 0, WaveBorder{}, v)) {
-            decide_region<kQueue>(a, img, im, x, y, w, h, level, false, v, lane);
-            return;
-        }
-        const uint32_t nseg = (nring + kSegPx - 1) / kSegPx;
-        const uint32_t rid = wave_add(&a.ctrl[kRecs], 1u);
-        if (rid >= a.rec_cap) {  // the host sizes the records; never write past them
-            wave_or(&a.ctrl[kOverflow], 4u);
-            wave_or(&a.ctrl[kSticky], kErrOverflow);
-            return;
-        }
-        RingRec *rec = a.recs + rid;
-        *rec = RingRec{img, xy, wh, level, v, nseg, 0u, 0u};
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        emit_entries<true>(a, nseg - 1, kSeg, level, lane, [&](uint32_t j, Region &e) {
-            e.img = rid;
-            e.xy = (j + 1) | (nseg << 16);
-            e.wh = 0;
-            return true;
-        });
-        scan_segment(a, rid, 0, nseg, lane);
-        return;
-    }
-    const bool same = scan_ring(a, im, x, y, w, h, 0, 1, 0, WaveBorder{}, v);
+    const bool same = scan_ring(a, im, x, y, w, h, v);
     decide_region<kQueue>(a, img, im, x, y, w, h, level, same, v, lane);
 }
 
@@ -670,12 +585,13 @@ __global__ __launch_bounds__(kBlock) void level_exact_kernel(SubdivArgs a, uint3
     process_region<false>(a, a.in[idx], lane);
 }
 
-// Persistent kernel: every wave takes the next queue slot, waits until the
-// slot is published (its tag carries this launch's epoch), processes the
-// region and appends its children to the queue. `pending` counts regions
-// queued or in progress; a producer adds its children to it before it
-// removes itself, so pending reaches 0 only when no region is left or can
-// still be published, and then every waiting wave leaves.
+// Persistent kernel: every wave takes the next queue slot (one atomic add, a
+// ticket), waits until the slot is published (its tag carries this launch's
+// epoch), processes the region and appends its children to the queue.
+// `pending` counts entries queued or in progress; a producer adds its
+// children to it before it removes itself, so pending reaches 0 only when no
+// entry is left or can still be published, and then every waiting wave
+// leaves.
 //
 // Waiting is cheap on purpose: the slot's tag and `pending` are read with
 // relaxed loads (no cache invalidation), with a growing pause between reads,
@@ -694,7 +610,7 @@ __global__ __launch_bounds__(kBlock) void persistent_kernel(SubdivArgs a) {
     for (;;) {
         // Every lane runs the wait; the values it reads are made uniform.
         const uint32_t idx = wave_add(&ctrl[kHead], 1u);
-        const uint64_t t0 = clock_now();
+        const unsigned long long t0 = clock_now();
         uint32_t nap = 1, polls = 0;
         bool ready = false;
         for (;;) {
@@ -729,14 +645,16 @@ __global__ __launch_bounds__(kBlock) void persistent_kernel(SubdivArgs a) {
 // ---------------------------------------------------------------------------
 // Serving kernel: continuous batching into one persistent kernel.
 //
-// Every wave loops: take a region of the oldest admitted request that has
-// one (a compare-and-swap on that request's {gen, head} word, so a wave that
-// read a slot before it was reused can never take an entry of the slot's
-// next request), process it exactly as the persistent kernel does, with the
-// request's own queue, records and counters, and count it done. Between
-// regions, one wave at a time (at most every poll_ticks) reads the host's
-// mailbox and admits posted requests into free slots. The wave that counts a
-// request's last region done reports the request to the host.
+// Every wave loops: pick the oldest admitted request with a queue entry not
+// yet taken, take a reference to its slot (so that the slot cannot be handed
+// to another request while the wave may still touch it), take a ticket (one
+// atomic add on the request's head), process the entry exactly as the
+// persistent kernel does, with the request's own queue and counters, and
+// drop the reference. Between entries, one wave at a time (at most every
+// poll_ticks) reads the host's mailbox and admits posted requests into free
+// slots. The wave that counts a request's last entry done reports the
+// request to the host; the last wave to drop a reference to the finished
+// request frees its slot.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ unsigned long long uniform64(unsigned long long v) {
     return ((unsigned long long)uniform((uint32_t)(v >> 32)) << 32) | uniform((uint32_t)v);
@@ -786,11 +704,11 @@ __device__ __forceinline__ SubdivArgs slot_args(const ServerArgs &sa, ServerSlot
     a.nimg = 1;
     a.queue = sa.queue + post.qoff;
     a.cap = post.qcap;
-    a.recs = sa.recs + post.roff;
-    a.rec_cap = post.rcap;
     a.epoch = gen;
     a.wait_ticks = sa.wait_ticks;
     a.ctrl = sl->ctrl;
+    a.leaf_band = kLeafTask;
+    a.leaf_min = kLeafTask;
     return a;
 }
 
@@ -804,9 +722,11 @@ __device__ void admit(const ServerArgs &sa, uint32_t k, uint32_t gen, uint32_t l
     store_words(&sl->post, post);
     const Image &im = post.im;
     const uint32_t g = im.g, nseed = g * g;
+    // The reference word is left alone: a wave that read the slot before it
+    // was freed may still add and drop a reference.
     for (uint32_t i = lane; i < kCtrlWords; i += kWave)
-        sl->ctrl[i] = (i == kTail || i == kPending) ? nseed : 0u;
-    sl->claim = (unsigned long long)gen << 32;
+        if (i != kRefs)
+            sl->ctrl[i] = (i == kTail || i == kPending) ? nseed : 0u;
     Region *q = sa.queue + post.qoff;
     for (uint32_t j = lane; j < nseed; j += kWave) {
         const uint32_t jx = j % g, jy = j / g;
@@ -855,15 +775,16 @@ __device__ bool poll_mailbox(const ServerArgs &sa, uint32_t lane) {
     return any;
 }
 
-// Report request k as finished: free its slot for the next admission, then
-// make its image visible beyond the device and tell the host.
+// Report request k as finished: mark its slot done, then make its image
+// visible beyond the device and tell the host. The slot is freed by the last
+// wave that drops its reference.
 __device__ void finish_request(const ServerArgs &sa, ServerSlot *sl, uint32_t k, uint32_t gen) {
     const uint32_t err = uniform(__hip_atomic_load(&sl->ctrl[kSticky], __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_AGENT));
     const int32_t status = (err & kErrTimeout)    ? (int32_t)ASK_ETIMEOUT
                            : (err & kErrOverflow) ? (int32_t)ASK_EOVERFLOW
                                                   : (int32_t)ASK_OK;
-    __hip_atomic_store(&sa.ctl->state[k], (gen << 8) | kSlotFree, __ATOMIC_RELAXED,
+    __hip_atomic_store(&sa.ctl->state[k], (gen << 8) | kSlotDone, __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
     const unsigned long long t = clock_now();
     if (first_lane()) {
@@ -876,34 +797,72 @@ __device__ void finish_request(const ServerArgs &sa, ServerSlot *sl, uint32_t k,
     }
 }
 
-// Process entry idx of request k (generation gen), taken by this wave.
-__device__ void serve_entry(const ServerArgs &sa, uint32_t k, uint32_t gen, uint32_t idx,
-                            uint32_t lane) {
+// Take a reference to slot k while it holds request gen; false (and no
+// reference) if it no longer does.
+__device__ bool take_ref(const ServerArgs &sa, uint32_t k, uint32_t gen) {
+    ServerSlot *sl = sa.slots + k;
+    if (first_lane())
+        __hip_atomic_fetch_add(&sl->ctrl[kRefs], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t st = uniform(__hip_atomic_load(&sa.ctl->state[k], __ATOMIC_ACQUIRE,
+                                                  __HIP_MEMORY_SCOPE_AGENT));
+    return st == ((gen << 8) | kSlotActive);
+}
+
+// Drop a reference to slot k. The wave that drops the last reference frees
+// the slot if it holds a finished request (whichever: a wave whose reference
+// was taken for an older request may be the last). A request is marked done
+// before its finishing wave drops its own reference, so when the count
+// reaches 0 after that, the dropping wave sees the mark.
+__device__ void drop_ref(const ServerArgs &sa, uint32_t k) {
+    ServerSlot *sl = sa.slots + k;
+    uint32_t old = 0;
+    if (first_lane())
+        old = __hip_atomic_fetch_add(&sl->ctrl[kRefs], (uint32_t)-1, __ATOMIC_ACQ_REL,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+    if (uniform(old) != 1u)
+        return;
+    const uint32_t st = uniform(__hip_atomic_load(&sa.ctl->state[k], __ATOMIC_ACQUIRE,
+                                                  __HIP_MEMORY_SCOPE_AGENT));
+    if (slot_kind(st) == kSlotDone && first_lane())
+        atomicCAS(&sa.ctl->state[k], st, (st & ~0xffu) | kSlotFree);
+}
+
+// Serve ticket idx of request k (generation gen), holding a reference to
+// the slot: wait until the entry is published (or the request has finished,
+// when the ticket lies beyond its last entry), process it and count it done.
+__device__ void serve_ticket(const ServerArgs &sa, uint32_t k, uint32_t gen, uint32_t idx,
+                             uint32_t lane) {
     ServerSlot *sl = sa.slots + k;
     const ServerPost post = load_words<ServerPost, __HIP_MEMORY_SCOPE_AGENT>(&sl->post);
     const SubdivArgs a = slot_args(sa, sl, post, gen);
-    // The entry is below the tail, so its producer has reserved it; wait
-    // until it is written.
-    const uint64_t t0 = clock_now();
-    uint32_t nap = 1;
+    const unsigned long long t0 = clock_now();
+    uint32_t nap = 1, polls = 0;
     bool ready = false;
     for (;;) {
-        const uint32_t t = uniform(__hip_atomic_load(&a.queue[idx].tag, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT));
-        if ((t >> 8) == gen) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            ready = true;
-            break;
+        if (idx < a.cap) {
+            const uint32_t t = uniform(__hip_atomic_load(&a.queue[idx].tag, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT));
+            if ((t >> 8) == gen) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                ready = true;
+                break;
+            }
         }
-        if (clock_now() - t0 > a.wait_ticks)
-            break;
+        if ((++polls & 7) == 0 || idx >= a.cap) {
+            if (uniform(__hip_atomic_load(&sl->ctrl[kPending], __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT)) == 0)
+                return;  // the request has finished: no entry will come
+            if (clock_now() - t0 > a.wait_ticks) {
+                // Never expected: the request cannot finish without this entry.
+                wave_or(&sl->ctrl[kSticky], kErrTimeout);
+                break;
+            }
+        }
         pause(nap);
         nap = min(nap * 2, 32u);
     }
     if (ready)
         process_region<true>(a, a.queue[idx], lane);
-    else
-        wave_or(&sl->ctrl[kSticky], kErrTimeout);
     // Count the entry done, releasing this wave's writes; the last one also
     // acquires everyone else's.
     uint32_t left = 0;
@@ -934,38 +893,36 @@ __global__ __launch_bounds__(kBlock) void server_kernel(ServerArgs sa) {
                 nap = 1;
             }
         }
-        // Lane k looks at slot k: active, of its generation, and with an
-        // entry reserved below the tail (and inside the queue) not yet taken.
-        uint32_t st = 0, lim = 0;
-        unsigned long long hc = 0;
+        // Lane k looks at slot k: an active request with an entry reserved
+        // below its tail (and inside its queue) not yet taken.
+        uint32_t st = 0;
+        bool avail = false;
         if (lane < sa.nslots) {
             st = __hip_atomic_load(&sa.ctl->state[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (slot_kind(st) == kSlotActive) {
                 ServerSlot *sl = sa.slots + lane;
-                hc = __hip_atomic_load(&sl->claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                lim = min(__hip_atomic_load(&sl->ctrl[kTail], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-                          __hip_atomic_load(&sl->post.qcap, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                const uint32_t head = __hip_atomic_load(&sl->ctrl[kHead], __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t lim = min(__hip_atomic_load(&sl->ctrl[kTail], __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT),
+                                         __hip_atomic_load(&sl->post.qcap, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT));
+                avail = head < lim;
             }
         }
-        const bool avail = slot_kind(st) == kSlotActive && (uint32_t)(hc >> 32) == slot_gen(st) &&
-                           (uint32_t)hc < lim;
         if (__ballot(avail)) {
             // The oldest request first: the least generation (the host hands
             // them out in order and restarts the server before they wrap).
             const uint32_t oldest = uniform(wave_min(avail ? slot_gen(st) : 0xffffffffu));
             const uint32_t k = uniform((uint32_t)__builtin_ctzll(__ballot(avail && slot_gen(st) == oldest)));
-            const unsigned long long hk =
-                ((unsigned long long)__builtin_amdgcn_readlane((uint32_t)(hc >> 32), k) << 32) |
-                __builtin_amdgcn_readlane((uint32_t)hc, k);
-            unsigned long long old = ~hk;
-            if (first_lane())
-                old = atomicCAS(&sa.slots[k].claim, hk, hk + 1);
-            if (uniform64(old) != hk)
-                continue;  // another wave took it first: look again
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the slot's post and counters
-            serve_entry(sa, k, (uint32_t)(hk >> 32), (uint32_t)hk, lane);
-            __hip_atomic_store(&sa.ctl->last_busy, clock_now(),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (take_ref(sa, k, oldest)) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the slot's post and counters
+                const uint32_t idx = wave_add(&sa.slots[k].ctrl[kHead], 1u);
+                serve_ticket(sa, k, oldest, idx, lane);
+                __hip_atomic_store(&sa.ctl->last_busy, clock_now(), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
+            drop_ref(sa, k);
             nap = 1;
             continue;
         }
@@ -978,7 +935,7 @@ __global__ __launch_bounds__(kBlock) void server_kernel(ServerArgs sa) {
             __hip_atomic_load(&sa.ctl->stop_time, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         const unsigned long long busy = uniform64(
             __hip_atomic_load(&sa.ctl->last_busy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-        const bool none = __ballot(slot_kind(st) != kSlotFree) == 0;
+        const bool none = __ballot(slot_kind(st) == kSlotActive || slot_kind(st) == kSlotAdmitting) == 0;
         // (The times were taken by other waves and may be a little later
         // than t.)
         const unsigned long long since_stop = t > stop_time ? t - stop_time : 0;

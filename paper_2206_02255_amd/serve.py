@@ -60,11 +60,12 @@ class Arena(FirstFit):
 
 
 def serve(ctx, schedule, params_of, slots=64, arena_bytes=16 << 30, pool_bytes=1 << 30,
-          keep=None, log=None):
+          keep=None, log=None, limit_s=120.0):
     """Run `schedule` [(arrival_s, window)] through a server on ctx.
 
     params_of(window) -> workloads.Params. keep(i) -> True to copy request
-    i's image to the host (returned in 'images'). Returns a dict of the
+    i's image to the host (returned in 'images'). Raises TimeoutError when
+    the run lasts limit_s beyond the last arrival. Returns a dict of the
     run's measurements."""
     import torch
     arena = Arena(torch, arena_bytes // 4)
@@ -79,8 +80,12 @@ def serve(ctx, schedule, params_of, slots=64, arena_bytes=16 << 30, pool_bytes=1
     t0 = time.perf_counter()
     last_log = t0
     try:
+        deadline = (schedule[-1][0] if n else 0.0) + limit_s
         while i < n or backlog or inflight:
             now = time.perf_counter() - t0
+            if now > deadline:
+                raise TimeoutError("serving did not finish: %d of %d done, %d in flight"
+                                   % (len(lat), n, len(inflight)))
             while i < n and schedule[i][0] <= now:
                 backlog.append(i)
                 i += 1
