@@ -77,6 +77,7 @@ def parse():
     ap.add_argument("--batch-count", type=int, default=256,
                     help="images of the batched workload (0: skip it)")
     ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--no-deep", action="store_true", help="skip the deep-zoom image")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first copy BYTES of device memory once (a plain copy kernel of known "
                          "size, to scale the memory-traffic counters of a profile)")
@@ -140,6 +141,44 @@ def batched_leg(ctx, torch, ask, workloads, sp, count, steps):
             "one_by_one_levels_ms": round(seq_lv_ms, 3),
             "speedup_vs_one_by_one_levels": round(seq_lv_ms / ms, 2),
             "equals_one_by_one": same}
+
+
+def deep_leg(ctx, torch, ask, workloads, sp):
+    """The deep-zoom image (32768^2, width 1e-6 around a boundary point,
+    D = 8192): exhaustive kernel, persistent and per-level subdivision."""
+    w = workloads.deep_window()
+    p = workloads.DEEP_PARAMS
+    win = ask.window(w)
+    out = torch.empty(w.W * w.H, dtype=torch.int32, device="cuda")
+    log("deep: %s, exhaustive" % (w,))
+    ask.ask_enable_timing(ctx, True)
+    ask.ask_dwell_exhaustive(ctx, win, out.data_ptr(), sp)
+    ex_ms = ask.ask_last_kernel_ms(ctx)
+    ex_iters = int(out.to(torch.int64).sum().item())
+    ex = out.clone()
+    res = {"workload": "mandelbrot-deep-32768x32768-D8192-width1e-6", "g": p.g, "r": p.r, "B": p.B,
+           "exhaustive": {"kernel_ms": round(ex_ms, 2), "dwell_iterations": ex_iters,
+                          "fp64_frac": round(FLOPS_PER_ITERATION * ex_iters / (ex_ms * 1e-3) / 1e12
+                                             / PEAK_FP64_TFLOPS, 4)}}
+    for form in ("persistent", "levels"):
+        log("deep: %s" % form)
+        prm = ask.params(p.g, p.r, p.B, form)
+        st = ask.ask_dwell_subdiv(ctx, win, prm, out.data_ptr(), sp, want_stats=True)
+        iters = st["iters_ring"] + st["iters_leaf"]
+        ms = []
+        for _ in range(2):
+            ask.ask_dwell_subdiv(ctx, win, prm, out.data_ptr(), sp)
+            ms.append(ask.ask_last_kernel_ms(ctx))
+        res[form] = {"kernel_ms": round(min(ms), 2), "dwell_iterations": iters,
+                     "mpix_s": round(w.pixels / (min(ms) * 1e-3) / 1e6, 1),
+                     "fp64_frac": round(FLOPS_PER_ITERATION * iters / (min(ms) * 1e-3) / 1e12
+                                        / PEAK_FP64_TFLOPS, 4),
+                     "speedup_vs_exhaustive": round(ex_ms / min(ms), 3),
+                     "pixels_differing_from_exhaustive": int((out != ex).sum().item())}
+    ask.ask_enable_timing(ctx, False)
+    ask.ask_synchronize(ctx, sp)
+    del out, ex
+    return res
 
 
 def served_leg(ctx, ask, workloads, seconds):
@@ -286,6 +325,8 @@ def main():
                                                  args.batch_steps)
     if args.serve_seconds > 0:
         result["forms"]["served"] = served_leg(ctx, ask, workloads, args.serve_seconds)
+    if not args.no_deep:
+        result["forms"]["deep"] = deep_leg(ctx, torch, ask, workloads, sp)
 
     if not args.no_cpu_baseline:
         import numpy as np

@@ -238,6 +238,33 @@ def test_large_paper_window_sampled(gpu, ref, form, g, r, B):
     assert np.array_equal(img[:64], img[::-1][:64])
 
 
+def test_deep_window_sampled(gpu, ref):
+    # 32768 x 32768 around a boundary point, width 1e-6, D = 8192, in the
+    # bench's launch configuration: sampled pixels against the oracle's tree
+    # descent (subdivision) and dwell (exhaustive).
+    import workloads
+    ask, ctx, torch = gpu
+    w = workloads.deep_window()
+    p = workloads.DEEP_PARAMS
+    rng = np.random.default_rng(17)
+    px = rng.integers(0, w.W, 120)
+    py = rng.integers(0, w.H, 120)
+    out = torch.empty(w.W * w.H, dtype=torch.int32, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    idx = torch.as_tensor(py * w.W + px, device="cuda")
+
+    def sample():
+        torch.cuda.synchronize()
+        return out[idx].cpu().numpy().view(np.uint32)
+
+    ask.ask_dwell_subdiv(ctx, ask.window(w), ask.params(p.g, p.r, p.B, "persistent"),
+                         out.data_ptr(), s)
+    ask.ask_synchronize(ctx, s)
+    assert np.array_equal(sample(), ref.subdiv_pixels(w, p.g, p.r, p.B, px, py))
+    ask.ask_dwell_exhaustive(ctx, ask.window(w), out.data_ptr(), s)
+    assert np.array_equal(sample(), ref.dwell_pixels(w, px, py))
+
+
 def test_large_exhaustive_sampled(gpu, ref):
     w = LARGE
     img = gpu_exhaustive(gpu, w)

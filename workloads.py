@@ -134,6 +134,11 @@ def deep_window(seed=3, n=32768, D=8192, width=1e-6):
     return centred(cx, cy, width, n, n, D)
 
 
+# (g, r, B) for the deep-zoom image: the fastest of a measured sweep on
+# MI355X (near the boundary few regions are uniform, so wider leaves pay).
+DEEP_PARAMS = Params(64, 2, 64)
+
+
 def batch_params(side):
     """(g, r, B) for a batch or serving image of the given side: level-0
     regions of about 256 pixels, r = 2, B = 32 (the best setting of the
