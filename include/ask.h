@@ -143,7 +143,16 @@ ask_status ask_dwell_exhaustive(ask_ctx *ctx, const ask_window *win,
  * call wait for the stream and return any error the render recorded (as
  * ask_synchronize does). The call also waits for the stream when the queue
  * could overflow (very large images with tiny B); an overflow then returns
- * ASK_EOVERFLOW. Otherwise device-side errors surface at ask_synchronize. */
+ * ASK_EOVERFLOW. Otherwise device-side errors surface at ask_synchronize.
+ *
+ * Graphs: the call may be made on a stream that is capturing (HIP stream
+ * capture), for the levels and persistent forms, with stats == NULL, after
+ * one render of the same size outside the capture (so that no queue grows
+ * while capturing; ASK_EINVAL otherwise). The graph then replays the whole
+ * render; a captured persistent render clears its own queue at every replay.
+ * The context never frees a buffer that a captured render names (it only
+ * retires it until ask_destroy), so graphs stay valid while the context
+ * lives. */
 ask_status ask_dwell_subdiv(ask_ctx *ctx, const ask_window *win,
                             const ask_params *params, uint32_t *d_out,
                             void *stream, ask_stats *stats);
@@ -158,7 +167,9 @@ ask_status ask_dwell_subdiv(ask_ctx *ctx, const ask_window *win,
  * caller-owned; images must not overlap. stats (optional) sums the counters
  * over the batch and makes the call wait, as for ask_dwell_subdiv. The image
  * table is staged through context-owned pinned memory; the call returns
- * once the staging buffer is free for its copy. */
+ * once the staging buffer is free for its copy. A batch of more than one
+ * image cannot be captured into a graph (ASK_EINVAL on a capturing stream):
+ * its table is staged through memory that later calls reuse. */
 ask_status ask_dwell_batch(ask_ctx *ctx, uint32_t n, const ask_window *wins,
                            const ask_params *params, uint32_t nparams,
                            uint32_t *const *d_outs, void *stream, ask_stats *stats);

@@ -48,6 +48,11 @@ struct ask_ctx {
     // context (any stream): buffers are reallocated only after it.
     hipEvent_t last = nullptr;
     bool last_set = false;
+    // Once a render has been captured into a graph, the graph may replay it
+    // at any later time: buffers it names are never freed before the
+    // context, only retired.
+    bool captured = false;
+    std::vector<void *> retired;
     ask_server *server = nullptr;  // the context's server, if one runs
     char err[512] = {0};
 };
@@ -204,7 +209,10 @@ ask_status grow(ask_ctx *ctx, T **buf, size_t *cap, size_t need, bool clear) {
         e = wait_last(ctx);
         if (e != hipSuccess)
             return hip_fail(ctx, e, "hipEventSynchronize");
-        (void)hipFree(*buf);
+        if (ctx->captured)
+            ctx->retired.push_back(*buf);
+        else
+            (void)hipFree(*buf);
         *buf = nullptr;
         *cap = 0;
     }
@@ -275,6 +283,10 @@ ask_status read_stats(ask_ctx *ctx, hipStream_t s, ask_stats *out) {
 hipError_t mark(ask_ctx *ctx, int which, hipStream_t s) {
     if (!ctx->timing)
         return hipSuccess;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone)
+        return hipSuccess;  // a graph is not timed by the context's events
+    (void)hipGetLastError();
     if (which == 1)
         ctx->timed = true;
     return hipEventRecord(ctx->ev[which], s);
@@ -394,6 +406,8 @@ ask_status ask_destroy(ask_ctx *ctx) {
             (void)hipEventDestroy(ctx->staged);
         if (ctx->last)
             (void)hipEventDestroy(ctx->last);
+        for (void *p : ctx->retired)
+            (void)hipFree(p);
         (void)hipFree(ctx->table);
         (void)hipHostFree(ctx->staging);
     }
@@ -430,6 +444,20 @@ namespace {
 // the persistent kernel over one queue. `ims` holds each image's constants.
 ask_status render(ask_ctx *ctx, const Image *ims, uint32_t n, uint32_t form, hipStream_t s,
                   ask_stats *stats) {
+    // Under stream capture the render becomes a graph that may replay many
+    // times: nothing may wait, allocate or stage data that a later call could
+    // change, and the persistent queue is cleared by a kernel of the graph
+    // (its slots then carry a launch epoch reserved for graphs).
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess) {
+        (void)hipGetLastError();
+        cap = hipStreamCaptureStatusNone;
+    }
+    const bool capturing = cap != hipStreamCaptureStatusNone;
+    if (capturing && (stats || n > 1 || form == ASK_FORM_LEVELS_READBACK))
+        return fail(ctx, ASK_EINVAL,
+                    "a captured render takes one image, no work counters and not the read-back "
+                    "form%s", nullptr);
     uint32_t levels = 0;
     uint64_t nseeds = 0;
     Bounds b;
@@ -450,6 +478,11 @@ ask_status render(ask_ctx *ctx, const Image *ims, uint32_t n, uint32_t form, hip
     const uint64_t need = form == ASK_FORM_PERSISTENT ? b.queue_entries(kLeafTask) : widest;
     const uint64_t want = std::min<uint64_t>(need, kQueueBudget);
     const bool may_overflow = need > want;
+    if (capturing && (may_overflow || (form == ASK_FORM_PERSISTENT ? ctx->queue_cap < want
+                                                                   : ctx->lvq_cap < want)))
+        return fail(ctx, ASK_EINVAL,
+                    "render once outside the capture first (the queues must not grow "
+                    "while capturing)%s", nullptr);
     ask_status st;
     if (form == ASK_FORM_PERSISTENT) {
         st = grow(ctx, &ctx->queue, &ctx->queue_cap, want, true);
@@ -523,18 +556,28 @@ ask_status render(ask_ctx *ctx, const Image *ims, uint32_t n, uint32_t form, hip
         return hip_fail(ctx, e, "reset kernel launch");
 
     if (form == ASK_FORM_PERSISTENT) {
-        ctx->epoch = (ctx->epoch + 1) & 0xffffffu;
-        if (ctx->epoch == 0) {  // tags wrapped: clear the queue once
-            e = hipMemsetAsync(ctx->queue, 0, ctx->queue_cap * sizeof(Region), s);
+        uint32_t epoch;
+        if (capturing) {
+            ctx->captured = true;
+            e = launch_clear_queue(ctx->queue, (uint32_t)ctx->queue_cap, s);
             if (e != hipSuccess)
-                return hip_fail(ctx, e, "hipMemsetAsync");
-            ctx->epoch = 1;
+                return hip_fail(ctx, e, "queue clear launch");
+            epoch = kGraphEpoch;
+        } else {
+            ctx->epoch = (ctx->epoch + 1) & 0xffffffu;
+            if (ctx->epoch == 0 || ctx->epoch == kGraphEpoch) {  // wrapped: clear the queue once
+                e = hipMemsetAsync(ctx->queue, 0, ctx->queue_cap * sizeof(Region), s);
+                if (e != hipSuccess)
+                    return hip_fail(ctx, e, "hipMemsetAsync");
+                ctx->epoch = 1;
+            }
+            epoch = ctx->epoch;
         }
         a.queue = ctx->queue;
         a.cap = (uint32_t)std::min<size_t>(ctx->queue_cap, 0xffffffffu - 65536u);
         a.leaf_band = kLeafTask;
         a.leaf_min = kLeafTask;
-        a.epoch = ctx->epoch;
+        a.epoch = epoch;
         a.wait_ticks = (uint64_t)(ctx->wait_limit_s * ctx->clock_hz);
         e = launch_seed_queue(a, (uint32_t)nseeds, s);
         if (e == hipSuccess)
@@ -582,6 +625,10 @@ ask_status render(ask_ctx *ctx, const Image *ims, uint32_t n, uint32_t form, hip
         e = mark(ctx, 1, s);
         if (e != hipSuccess)
             return hip_fail(ctx, e, "hipEventRecord");
+    }
+    if (capturing) {
+        ctx->captured = true;
+        return ASK_OK;
     }
     e = note_last(ctx, s);
     if (e != hipSuccess)

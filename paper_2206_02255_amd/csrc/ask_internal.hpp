@@ -38,6 +38,10 @@ enum Kind : uint32_t { kScan = 0, kLeaf = 1 };
 // so that no wave holds a whole large leaf while others idle.
 constexpr uint32_t kLeafTask = 1024;
 
+// Launch epoch of persistent renders captured in a graph (whose queue is
+// cleared by the graph itself); other renders cycle through 1 .. kGraphEpoch - 1.
+constexpr uint32_t kGraphEpoch = 0xffffffu;
+
 __host__ __device__ inline uint32_t pack_xy(uint32_t x, uint32_t y) { return x | (y << 16); }
 __host__ __device__ inline uint32_t pack_wh(uint32_t w, uint32_t h) { return (w - 1) | ((h - 1) << 16); }
 
@@ -155,6 +159,7 @@ hipError_t occupancy_server(int *blocks_per_cu);
 // Kernel launchers (ask_kernels.hip). All return hipSuccess or the launch error.
 hipError_t launch_exhaustive(const Image &im, hipStream_t s);
 hipError_t launch_reset(uint32_t *ctrl, DevStats *stats, hipStream_t s);
+hipError_t launch_clear_queue(Region *queue, uint32_t entries, hipStream_t s);
 hipError_t launch_seed_levels(const SubdivArgs &a, uint32_t nseeds, hipStream_t s);
 hipError_t launch_seed_queue(const SubdivArgs &a, uint32_t nseeds, hipStream_t s);
 hipError_t launch_level(const SubdivArgs &a, uint32_t grid_blocks, hipStream_t s);

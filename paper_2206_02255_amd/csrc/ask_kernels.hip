@@ -962,6 +962,14 @@ __global__ void reset_kernel(uint32_t *ctrl, DevStats *stats) {
     }
 }
 
+// Every entry of a queue zeroed (no slot then carries a launch epoch): the
+// persistent queue of a render captured in a graph, cleared by the graph.
+__global__ void clear_queue_kernel(uint4 *q, uint32_t entries) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < entries)
+        q[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 // Level 0 (Sec. 4.2: G = g x g initial regions): the floor partition of each
 // image. Seed i belongs to the image whose seed range holds it.
 template <bool kQueue>
@@ -1015,6 +1023,13 @@ hipError_t launch_exhaustive(const Image &im, hipStream_t s) {
 
 hipError_t launch_reset(uint32_t *ctrl, DevStats *stats, hipStream_t s) {
     hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(kBlock), 0, s, ctrl, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_queue(Region *queue, uint32_t entries, hipStream_t s) {
+    const uint32_t blocks = (entries + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(clear_queue_kernel, dim3(blocks ? blocks : 1), dim3(kBlock), 0, s,
+                       reinterpret_cast<uint4 *>(queue), entries);
     return hipGetLastError();
 }
 
