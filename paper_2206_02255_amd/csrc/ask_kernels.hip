@@ -206,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void exhaustive_kernel(Image im) {
 // `partial` receives, per lane, the iterations of a pixel left unfinished by
 // an early stop (work done, for the counters).
 // ---------------------------------------------------------------------------
-constexpr uint32_t kRoundBlocks = 2;
+constexpr uint32_t kRoundBlocks = 4;
 
 // Border policies of dwell_stream: a leaf stream has none; a ring stream
 // decides uniformity against its first finished dwell.
