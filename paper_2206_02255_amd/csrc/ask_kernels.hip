@@ -251,7 +251,12 @@ __device__ __forceinline__ bool dwell_stream(const Image &im, uint32_t n, PixelO
         uint32_t dw = 0;
         bool fin = false;
         if (have) {
-            for (uint32_t bi = 0; bi < kRoundBlocks && !fin; ++bi) {
+            // A lane whose pixel escapes inside a stretch goes back to the
+            // stretch's start and leaves the loop; the replay that finds the
+            // first k follows the loop, once per round for all such lanes
+            // rather than once in every stretch in which some lane escaped.
+            bool replay = false;
+            for (uint32_t bi = 0; bi < kRoundBlocks && !fin && !replay; ++bi) {
                 if (__builtin_expect(!special, 1)) {
                     const double szr = zr, szi = zi, szr2 = zr2, szi2 = zi2;
 #pragma unroll
@@ -263,13 +268,11 @@ __device__ __forceinline__ bool dwell_stream(const Image &im, uint32_t n, PixelO
                         zi2 = zi * zi;
                     }
                     if (!(zr2 + zi2 <= 4.0)) {
-                        // escaped inside the stretch: find the first k again
                         zr = szr;
                         zi = szi;
                         zr2 = szr2;
                         zi2 = szi2;
-                        dw = dwell_from(cr, ci, D, kbase, zr, zi, zr2, zi2);
-                        fin = true;
+                        replay = true;
                     } else {
                         kbase += kStride;
                     }
@@ -289,6 +292,10 @@ __device__ __forceinline__ bool dwell_stream(const Image &im, uint32_t n, PixelO
                     if (!fin)
                         kbase += kStride;
                 }
+            }
+            if (replay) {
+                dw = dwell_from(cr, ci, D, kbase, zr, zi, zr2, zi2);
+                fin = true;
             }
             if (!fin && kbase >= D) {
                 dw = D;
