@@ -158,6 +158,14 @@ __device__ __forceinline__ void wave_max(uint32_t *p, uint32_t v) {
         atomicMax(p, v);
 }
 
+// A dwell written to the image in device memory with a global store. Through
+// a generic pointer the store would be a flat one, which also counts on the
+// counter of scalar and LDS operations: every later wait on those (a scalar
+// load, a lane permute) would then also wait for the store to complete.
+__device__ __forceinline__ void put_dwell(uint32_t *out, size_t i, uint32_t d) {
+    ((__attribute__((address_space(1))) uint32_t *)out)[i] = d;
+}
+
 // ---------------------------------------------------------------------------
 // Exhaustive image (Sec. 4.1): one lane per pixel. A 256-lane workgroup owns
 // a 16 x 16 tile; each wave a 16 x 4 strip of it.
@@ -171,7 +179,7 @@ __global__ __launch_bounds__(kBlock) void exhaustive_kernel(Image im) {
         return;
     double cr, ci;
     pixel_c(im, px, py, cr, ci);
-    im.out[(size_t)py * im.W + px] = dwell(cr, ci, im.D);
+    put_dwell(im.out, (size_t)py * im.W + px, dwell(cr, ci, im.D));
 }
 
 
@@ -367,14 +375,14 @@ __device__ void fill_region(uint32_t *out, uint32_t W, uint32_t x, uint32_t y, u
         for (uint32_t row = 0; row < h; ++row) {
             uint32_t *p = out + (size_t)(y + row) * W + x;
             for (uint32_t c = lane; c < w; c += kWave)
-                p[c] = v;
+                put_dwell(p, c, v);
         }
     } else {
         const uint32_t per = kWave / w;
         const uint32_t lr = lane / w, lc = lane - lr * w;
         if (lr < per)
             for (uint32_t row = lr; row < h; row += per)
-                out[(size_t)(y + row) * W + x + lc] = v;
+                put_dwell(out, (size_t)(y + row) * W + x + lc, v);
     }
 }
 
@@ -393,15 +401,35 @@ __device__ unsigned long long leaf_region(const Image &im, uint32_t x, uint32_t 
             return true;
         },
         [&](uint32_t px, uint32_t py, uint32_t d) {
-            im.out[(size_t)py * im.W + px] = d;
+            put_dwell(im.out, (size_t)py * im.W + px, d);
             it += d;
         },
         NoBorder{}, v, partial);
     return it;
 }
 
+// The image table is written before a launch and never by a kernel, so it is
+// read with scalar loads (constant address space): the image's fields live in
+// scalar registers, and no wait inside the pixel loops has to cover them.
 __device__ __forceinline__ Image image_of(const SubdivArgs &a, uint32_t img) {
-    return a.table ? a.table[img] : a.single;
+    if (a.table) {
+        const __attribute__((address_space(4))) Image &t =
+            ((const __attribute__((address_space(4))) Image *)a.table)[img];
+        Image im;
+        im.cxm = t.cxm;
+        im.cym = t.cym;
+        im.hx = t.hx;
+        im.hy = t.hy;
+        im.W = t.W;
+        im.H = t.H;
+        im.D = t.D;
+        im.g = t.g;
+        im.r = t.r;
+        im.B = t.B;
+        im.out = t.out;
+        return im;
+    }
+    return a.single;
 }
 
 // Append `count` entries (entry_of(j, e) fills e's img, xy and wh, or
@@ -522,22 +550,30 @@ __device__ void decide_region(const SubdivArgs &a, uint32_t img, const Image &im
         wave_add64(&st->splits[level], 1ull);
 }
 
-// Q over the whole ring, taken in a spread order: the first 64 pixels are
-// spaced evenly around the ring, the next 64 follow them, and so on, so that
-// a mixed ring is usually found mixed in the first round. Returns whether
-// every ring pixel finished with dwell v; adds the iterations done to the
-// counters.
+// Q over the whole ring, taken in a spread order. The ring is cut into 64
+// arcs of q pixels, one per lane of the first round, so the first 64 pixels
+// are spaced evenly around it; later rounds take, in every arc, the offsets
+// 0, q/2, q/4, 3q/4, q/8, ... (bit-reversed round numbers), so that after
+// 2^k rounds the pixels taken are spaced q/2^k apart. A mixed ring is found
+// mixed as soon as one of its pixels has a dwell other than the rest; on a
+// ring whose pixels mostly run to D this finds a short arc of other dwells
+// in a few rounds rather than after up to q rounds of D iterations each, and
+// those rings are the ones a split must wait for. Returns whether every ring
+// pixel finished with dwell v; adds the iterations done to the counters.
 __device__ bool scan_ring(const SubdivArgs &a, const Image &im, uint32_t x, uint32_t y,
                           uint32_t w, uint32_t h, uint32_t &v) {
     const uint32_t nring = ring_size(w, h);
     const uint32_t q = (nring + kWave - 1) / kWave;
+    const uint32_t bits = q > 1 ? 32u - (uint32_t)__builtin_clz(q - 1) : 0u;  // 2^bits >= q
     unsigned long long it = 0;
     uint32_t partial = 0;
     const bool same = dwell_stream(
-        im, q * kWave,
+        im, kWave << bits,
         [&](uint32_t j, uint32_t &px, uint32_t &py) {
-            const uint32_t t = (j % kWave) * q + j / kWave;
-            if (t >= nring)
+            const uint32_t round = j / kWave;
+            const uint32_t off = bits ? __brev(round) >> (32u - bits) : 0u;
+            const uint32_t t = (j % kWave) * q + off;
+            if (off >= q || t >= nring)
                 return false;
             ring_pixel(x, y, w, h, t, px, py);
             return true;
