@@ -1,6 +1,6 @@
 /*
  * askref.c -- CPU oracle for the Mandelbrot dwell image and its
- * Mariani-Silver subdivision image.
+ * Mariani-Silver subdivision image, and the same images of filled Julia sets.
  *
  * TEST INFRASTRUCTURE: the independent checker of the GPU library. Only the
  * test suite, the smoke check and the CPU-baseline leg of the benchmark load
@@ -56,7 +56,16 @@ void askref_pixel_c(const double m[4], uint32_t W, uint32_t H,
  * imaginary part, then the squared modulus, each operation rounded. */
 uint32_t askref_dwell(double cr, double ci, uint32_t D)
 {
-    double zr = 0.0, zi = 0.0;
+    return askref_dwell_julia(0.0, 0.0, cr, ci, D);
+}
+
+/* The dwell in the filled Julia set of c (the other escape-time workload of
+ * the same class): iterate z <- z^2 + c from z = z0 and return the first
+ * count k >= 1 at which |z_k|^2 exceeds 4, or D. Each iteration: three
+ * products, then the real and the imaginary part, then the squared modulus,
+ * each operation rounded. The Mandelbrot dwell above is this at z0 = 0. */
+uint32_t askref_dwell_julia(double zr, double zi, double cr, double ci, uint32_t D)
+{
     for (uint32_t k = 1; k <= D; ++k) {
         double zr2 = zr * zr;
         double zi2 = zi * zi;
@@ -68,6 +77,17 @@ uint32_t askref_dwell(double cr, double ci, uint32_t D)
             return k;
     }
     return D;
+}
+
+/* The dwell of pixel (px, py): its point is c (Mandelbrot) or z0 (Julia). */
+static uint32_t pixel_dwell(const double m[4], uint32_t W, uint32_t H, const askref_set *set,
+                            uint32_t px, uint32_t py, uint32_t D)
+{
+    double pr, pi;
+    askref_pixel_c(m, W, H, px, py, &pr, &pi);
+    if (set && set->julia)
+        return askref_dwell_julia(pr, pi, set->cr, set->ci, D);
+    return askref_dwell(pr, pi, D);
 }
 
 static int window_ok(double x0, double x1, double y0, double y1,
@@ -96,6 +116,7 @@ static int thread_count(int threads)
 
 typedef struct {
     const double *m;
+    const askref_set *set;
     uint32_t W, H, D;
     uint32_t *out;
     int tid, nthreads;
@@ -108,9 +129,7 @@ static void *ex_worker(void *arg)
     uint64_t it = 0;
     for (uint32_t py = (uint32_t)j->tid; py < j->H; py += (uint32_t)j->nthreads) {
         for (uint32_t px = 0; px < j->W; ++px) {
-            double cr, ci;
-            askref_pixel_c(j->m, j->W, j->H, px, py, &cr, &ci);
-            uint32_t d = askref_dwell(cr, ci, j->D);
+            uint32_t d = pixel_dwell(j->m, j->W, j->H, j->set, px, py, j->D);
             j->out[(uint64_t)py * j->W + px] = d;
             it += d;
         }
@@ -122,6 +141,13 @@ static void *ex_worker(void *arg)
 int askref_exhaustive(double x0, double x1, double y0, double y1,
                       uint32_t W, uint32_t H, uint32_t D,
                       uint32_t *out, uint64_t *iters_out, int threads)
+{
+    return askref_exhaustive_set(x0, x1, y0, y1, W, H, D, NULL, out, iters_out, threads);
+}
+
+int askref_exhaustive_set(double x0, double x1, double y0, double y1,
+                          uint32_t W, uint32_t H, uint32_t D, const askref_set *set,
+                          uint32_t *out, uint64_t *iters_out, int threads)
 {
     if (!window_ok(x0, x1, y0, y1, W, H, D) || !out)
         return -1;
@@ -138,7 +164,7 @@ int askref_exhaustive(double x0, double x1, double y0, double y1,
         return -1;
     }
     for (int t = 0; t < nt; ++t) {
-        jobs[t] = (ex_job){m, W, H, D, out, t, nt, 0};
+        jobs[t] = (ex_job){m, set, W, H, D, out, t, nt, 0};
         pthread_create(&th[t], NULL, ex_worker, &jobs[t]);
     }
     uint64_t total = 0;
@@ -157,13 +183,17 @@ void askref_dwell_pixels(double x0, double x1, double y0, double y1,
                          uint32_t W, uint32_t H, uint32_t D, uint64_t n,
                          const uint32_t *px, const uint32_t *py, uint32_t *out)
 {
+    askref_dwell_pixels_set(x0, x1, y0, y1, W, H, D, NULL, n, px, py, out);
+}
+
+void askref_dwell_pixels_set(double x0, double x1, double y0, double y1,
+                             uint32_t W, uint32_t H, uint32_t D, const askref_set *set,
+                             uint64_t n, const uint32_t *px, const uint32_t *py, uint32_t *out)
+{
     double m[4];
     askref_map(x0, x1, y0, y1, W, H, m);
-    for (uint64_t i = 0; i < n; ++i) {
-        double cr, ci;
-        askref_pixel_c(m, W, H, px[i], py[i], &cr, &ci);
-        out[i] = askref_dwell(cr, ci, D);
-    }
+    for (uint64_t i = 0; i < n; ++i)
+        out[i] = pixel_dwell(m, W, H, set, px[i], py[i], D);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -191,6 +221,7 @@ static int on_ring(uint32_t x, uint32_t y, uint32_t w, uint32_t h,
 
 typedef struct {
     const double *m;
+    const askref_set *set;
     uint32_t W, H, D, g, r, B;
     uint32_t *out;
     askref_region *recs;
@@ -216,9 +247,7 @@ static void record(const sd_ctx *c, const rect *R, uint32_t level,
 
 static uint32_t dwell_at(const sd_ctx *c, uint32_t px, uint32_t py)
 {
-    double cr, ci;
-    askref_pixel_c(c->m, c->W, c->H, px, py, &cr, &ci);
-    return askref_dwell(cr, ci, c->D);
+    return pixel_dwell(c->m, c->W, c->H, c->set, px, py, c->D);
 }
 
 /* Scan the ring of R (every pixel in the first or last column or row of R,
@@ -411,6 +440,16 @@ int64_t askref_subdiv(double x0, double x1, double y0, double y1,
                       uint32_t *out, askref_stats *stats,
                       askref_region *recs, uint64_t rec_cap)
 {
+    return askref_subdiv_set(x0, x1, y0, y1, W, H, D, NULL, g, r, B, order, threads, out,
+                             stats, recs, rec_cap);
+}
+
+int64_t askref_subdiv_set(double x0, double x1, double y0, double y1,
+                          uint32_t W, uint32_t H, uint32_t D, const askref_set *set,
+                          uint32_t g, uint32_t r, uint32_t B, int order, int threads,
+                          uint32_t *out, askref_stats *stats,
+                          askref_region *recs, uint64_t rec_cap)
+{
     if (!window_ok(x0, x1, y0, y1, W, H, D) || !out)
         return -1;
     if (g < 1 || g > W || g > H || r < 2 || B < 1 || (order != 0 && order != 1))
@@ -418,7 +457,7 @@ int64_t askref_subdiv(double x0, double x1, double y0, double y1,
     double m[4];
     askref_map(x0, x1, y0, y1, W, H, m);
     uint64_t rec_count = 0;
-    sd_ctx c = {m, W, H, D, g, r, B, out, recs, rec_cap, &rec_count};
+    sd_ctx c = {m, set, W, H, D, g, r, B, out, recs, rec_cap, &rec_count};
     askref_stats total;
     memset(&total, 0, sizeof(total));
 
@@ -514,13 +553,22 @@ int askref_subdiv_pixels(double x0, double x1, double y0, double y1,
                          uint64_t n, const uint32_t *px, const uint32_t *py,
                          uint32_t *out)
 {
+    return askref_subdiv_pixels_set(x0, x1, y0, y1, W, H, D, NULL, g, r, B, n, px, py, out);
+}
+
+int askref_subdiv_pixels_set(double x0, double x1, double y0, double y1,
+                             uint32_t W, uint32_t H, uint32_t D, const askref_set *set,
+                             uint32_t g, uint32_t r, uint32_t B,
+                             uint64_t n, const uint32_t *px, const uint32_t *py,
+                             uint32_t *out)
+{
     if (!window_ok(x0, x1, y0, y1, W, H, D))
         return -1;
     if (g < 1 || g > W || g > H || r < 2 || B < 1)
         return -1;
     double m[4];
     askref_map(x0, x1, y0, y1, W, H, m);
-    sd_ctx c = {m, W, H, D, g, r, B, NULL, NULL, 0, NULL};
+    sd_ctx c = {m, set, W, H, D, g, r, B, NULL, NULL, 0, NULL};
     sd_local L;
     memset(&L, 0, sizeof(L));
     seen_region *seen = NULL;

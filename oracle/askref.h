@@ -1,6 +1,6 @@
 /*
  * askref.h -- CPU oracle for the Mandelbrot dwell image and its
- * Mariani-Silver subdivision image.
+ * Mariani-Silver subdivision image, and the same images of filled Julia sets.
  *
  * TEST INFRASTRUCTURE. This is the independent checker of the GPU library:
  * only the test suite, the smoke check and the CPU-baseline leg of the
@@ -50,6 +50,16 @@ typedef struct askref_region {
     uint32_t level, kind, value, pad_;
 } askref_region;
 
+/* The escape-time set a window's points are iterated in. julia == 0: the
+ * Mandelbrot set, the pixel's point is c and z_0 = 0 (cr, ci unused).
+ * julia == 1: the filled Julia set of the fixed c = cr + i ci, the pixel's
+ * point is z_0. A NULL set means the Mandelbrot set. */
+typedef struct askref_set {
+    uint32_t julia;
+    uint32_t pad_;
+    double cr, ci;
+} askref_set;
+
 /* Pixel-centre mapping constants {cxm, cym, hx, hy} of a window. */
 void askref_map(double x0, double x1, double y0, double y1,
                 uint32_t W, uint32_t H, double m[4]);
@@ -61,6 +71,11 @@ void askref_pixel_c(const double m[4], uint32_t W, uint32_t H,
 /* Dwell of c: first k >= 1 with |z_k|^2 > 4 for z_0 = 0, z_k = z_{k-1}^2 + c;
  * D if there is none. */
 uint32_t askref_dwell(double cr, double ci, uint32_t D);
+
+/* Dwell of z0 in the filled Julia set of c: first k >= 1 with |z_k|^2 > 4
+ * for z_k = z_{k-1}^2 + c; D if there is none. askref_dwell(cr, ci, D) is
+ * askref_dwell_julia(0, 0, cr, ci, D). */
+uint32_t askref_dwell_julia(double zr0, double zi0, double cr, double ci, uint32_t D);
 
 /* Exhaustive image: out[py*W + px] = dwell(c(px, py)). Returns 0, or -1 on a
  * bad argument. iters_out (may be NULL) receives the sum of all dwells.
@@ -92,6 +107,24 @@ int askref_subdiv_pixels(double x0, double x1, double y0, double y1,
 void askref_dwell_pixels(double x0, double x1, double y0, double y1,
                          uint32_t W, uint32_t H, uint32_t D, uint64_t n,
                          const uint32_t *px, const uint32_t *py, uint32_t *out);
+
+/* The same four images for a window of the given set (NULL: Mandelbrot). */
+int askref_exhaustive_set(double x0, double x1, double y0, double y1,
+                          uint32_t W, uint32_t H, uint32_t D, const askref_set *set,
+                          uint32_t *out, uint64_t *iters_out, int threads);
+int64_t askref_subdiv_set(double x0, double x1, double y0, double y1,
+                          uint32_t W, uint32_t H, uint32_t D, const askref_set *set,
+                          uint32_t g, uint32_t r, uint32_t B, int order, int threads,
+                          uint32_t *out, askref_stats *stats,
+                          askref_region *recs, uint64_t rec_cap);
+int askref_subdiv_pixels_set(double x0, double x1, double y0, double y1,
+                             uint32_t W, uint32_t H, uint32_t D, const askref_set *set,
+                             uint32_t g, uint32_t r, uint32_t B,
+                             uint64_t n, const uint32_t *px, const uint32_t *py,
+                             uint32_t *out);
+void askref_dwell_pixels_set(double x0, double x1, double y0, double y1,
+                             uint32_t W, uint32_t H, uint32_t D, const askref_set *set,
+                             uint64_t n, const uint32_t *px, const uint32_t *py, uint32_t *out);
 
 #ifdef __cplusplus
 }

@@ -1,7 +1,9 @@
 """ctypes view of the CPU oracle ``libaskref.so`` (test infrastructure only).
 
 A window is any object with attributes ``x0, x1, y0, y1, W, H, D`` (the
-complex rectangle, the image size in pixels and the maximum dwell).
+complex rectangle, the image size in pixels and the maximum dwell) and,
+optionally, ``julia``: None for the Mandelbrot set (a pixel's point is c), or
+the pair (cr, ci) of the filled Julia set whose points z0 the pixels are.
 Images come back as ``numpy.uint32`` arrays of shape ``(H, W)``, row 0 on the
 ``y0`` side.
 """
@@ -38,6 +40,11 @@ class Stats(C.Structure):
             d[k] = list(getattr(self, k)[:n])
         d["iters_alg"] = self.iters_ring + self.iters_leaf
         return d
+
+
+class Set(C.Structure):
+    _fields_ = [("julia", C.c_uint32), ("pad_", C.c_uint32),
+                ("cr", C.c_double), ("ci", C.c_double)]
 
 
 REGION_DTYPE = np.dtype([("x", "<u4"), ("y", "<u4"), ("w", "<u4"), ("h", "<u4"),
@@ -77,12 +84,33 @@ def lib():
         L.askref_subdiv_pixels.restype = i32
         L.askref_dwell_pixels.argtypes = [d, d, d, d, u32, u32, u32, u64, p32, p32, p32]
         L.askref_dwell_pixels.restype = None
+        ps = C.POINTER(Set)
+        L.askref_dwell_julia.argtypes = [d, d, d, d, u32]
+        L.askref_dwell_julia.restype = u32
+        L.askref_exhaustive_set.argtypes = [d, d, d, d, u32, u32, u32, ps, p32, p64, i32]
+        L.askref_exhaustive_set.restype = i32
+        L.askref_subdiv_set.argtypes = [d, d, d, d, u32, u32, u32, ps, u32, u32, u32, i32, i32,
+                                        p32, C.POINTER(Stats), C.c_void_p, u64]
+        L.askref_subdiv_set.restype = C.c_int64
+        L.askref_subdiv_pixels_set.argtypes = [d, d, d, d, u32, u32, u32, ps, u32, u32, u32,
+                                               u64, p32, p32, p32]
+        L.askref_subdiv_pixels_set.restype = i32
+        L.askref_dwell_pixels_set.argtypes = [d, d, d, d, u32, u32, u32, ps, u64, p32, p32, p32]
+        L.askref_dwell_pixels_set.restype = None
         _lib = L
     return _lib
 
 
 def _win(w):
     return (float(w.x0), float(w.x1), float(w.y0), float(w.y1), int(w.W), int(w.H), int(w.D))
+
+
+def _set(w):
+    """The window's set as the oracle's struct, or None for the Mandelbrot set."""
+    j = getattr(w, "julia", None)
+    if j is None:
+        return None
+    return C.byref(Set(1, 0, float(j[0]), float(j[1])))
 
 
 def _p32(a):
@@ -108,12 +136,17 @@ def dwell(cr, ci, D):
     return int(lib().askref_dwell(float(cr), float(ci), int(D)))
 
 
+def dwell_julia(zr0, zi0, cr, ci, D):
+    return int(lib().askref_dwell_julia(float(zr0), float(zi0), float(cr), float(ci), int(D)))
+
+
 def exhaustive(w, threads=0):
     """(image, sum of dwells) of the exhaustive image."""
     x0, x1, y0, y1, W, H, D = _win(w)
     out = np.empty((H, W), dtype=np.uint32)
     it = C.c_uint64()
-    rc = lib().askref_exhaustive(x0, x1, y0, y1, W, H, D, _p32(out), C.byref(it), int(threads))
+    rc = lib().askref_exhaustive_set(x0, x1, y0, y1, W, H, D, _set(w), _p32(out), C.byref(it),
+                                     int(threads))
     if rc != 0:
         raise ValueError("askref_exhaustive rejected the window")
     return out, it.value
@@ -131,9 +164,9 @@ def subdiv(w, g, r, B, order="bfs", threads=0, records=False):
     while True:
         if records:
             recs = np.zeros(cap, dtype=REGION_DTYPE)
-        rc = lib().askref_subdiv(x0, x1, y0, y1, W, H, D, int(g), int(r), int(B), o,
-                                 int(threads), _p32(out), C.byref(st),
-                                 recs.ctypes.data if records else None, cap)
+        rc = lib().askref_subdiv_set(x0, x1, y0, y1, W, H, D, _set(w), int(g), int(r), int(B),
+                                     o, int(threads), _p32(out), C.byref(st),
+                                     recs.ctypes.data if records else None, cap)
         if rc < 0:
             raise ValueError("askref_subdiv rejected its arguments")
         if not records:
@@ -149,8 +182,8 @@ def subdiv_pixels(w, g, r, B, px, py):
     px = np.ascontiguousarray(px, dtype=np.uint32)
     py = np.ascontiguousarray(py, dtype=np.uint32)
     out = np.empty(px.shape, dtype=np.uint32)
-    rc = lib().askref_subdiv_pixels(x0, x1, y0, y1, W, H, D, int(g), int(r), int(B),
-                                    px.size, _p32(px), _p32(py), _p32(out))
+    rc = lib().askref_subdiv_pixels_set(x0, x1, y0, y1, W, H, D, _set(w), int(g), int(r),
+                                        int(B), px.size, _p32(px), _p32(py), _p32(out))
     if rc != 0:
         raise ValueError("askref_subdiv_pixels rejected its arguments")
     return out
@@ -162,5 +195,6 @@ def dwell_pixels(w, px, py):
     px = np.ascontiguousarray(px, dtype=np.uint32)
     py = np.ascontiguousarray(py, dtype=np.uint32)
     out = np.empty(px.shape, dtype=np.uint32)
-    lib().askref_dwell_pixels(x0, x1, y0, y1, W, H, D, px.size, _p32(px), _p32(py), _p32(out))
+    lib().askref_dwell_pixels_set(x0, x1, y0, y1, W, H, D, _set(w), px.size, _p32(px), _p32(py),
+                                  _p32(out))
     return out

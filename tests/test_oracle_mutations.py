@@ -43,11 +43,15 @@ MUTANTS = {
         "        for (uint32_t py = R->y; py + 1 < R->y + R->h; ++py)\n"
         "            for (uint32_t px = R->x; px < R->x + R->w; ++px)\n"
         "                c->out[(uint64_t)py * c->W + px] = v;"),
+    "julia_z0_and_c_swapped": ("return askref_dwell_julia(pr, pi, set->cr, set->ci, D);",
+                               "return askref_dwell_julia(set->cr, set->ci, pr, pi, D);"),
+    "julia_set_ignored": ("if (set && set->julia)", "if (set && !set->julia)"),
     "ring_new_counts_parent_ring": ("if (R->pw == 0 || !on_ring(R->px, R->py, R->pw, R->ph, px, py))",
                                     "if (R->pw == 0 || on_ring(R->px, R->py, R->pw, R->ph, px, py))"),
 }
 
-PIN_TESTS = ["tests/test_oracle_dwell.py", "tests/test_oracle_subdiv.py"]
+PIN_TESTS = ["tests/test_oracle_dwell.py", "tests/test_oracle_subdiv.py",
+             "tests/test_oracle_julia.py"]
 
 
 def run_mutant(name, tmpdir):

@@ -22,7 +22,9 @@ import numpy as np
 @dataclass(frozen=True)
 class Window:
     """Complex rectangle [x0, x1] x [y0, y1] rendered at W x H pixels with
-    maximum dwell D. Row 0 of an image lies on the y0 side."""
+    maximum dwell D. Row 0 of an image lies on the y0 side. julia is None for
+    the Mandelbrot set (a pixel's point is c), or (cr, ci): the filled Julia
+    set of that c, whose points z0 the pixels are."""
     x0: float
     x1: float
     y0: float
@@ -30,6 +32,7 @@ class Window:
     W: int
     H: int
     D: int
+    julia: tuple = None
 
     @property
     def pixels(self):
