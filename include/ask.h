@@ -55,13 +55,23 @@ typedef enum ask_status {
     ASK_ETIMEOUT = -6   /* a wait ran out of time */
 } ask_status;
 
+/* The escape-time set whose dwell image a window samples (the paper's
+ * self-similar workload class). In both, z_k = z_{k-1}^2 + c and the dwell
+ * of a pixel is the first k >= 1 with |z_k|^2 > 4, or D if there is none.
+ *   ASK_SET_MANDELBROT: the pixel's point is c, and z_0 = 0 (Sec. 6).
+ *   ASK_SET_JULIA: the filled Julia set of the window's fixed c = (cr, ci);
+ *   the pixel's point is z_0. */
+enum { ASK_SET_MANDELBROT = 0, ASK_SET_JULIA = 1 };
+
 /* A complex window [x0, x1] x [y0, y1] rendered at W x H pixels with
  * maximum dwell D. Valid: finite bounds, x0 < x1, y0 < y1,
- * 1 <= W, H <= 65536, 1 <= D <= 2^31 - 1. */
+ * 1 <= W, H <= 65536, 1 <= D <= 2^31 - 1, set one of ASK_SET_*, and for
+ * ASK_SET_JULIA finite cr, ci. A zeroed set field is the Mandelbrot set. */
 typedef struct ask_window {
     double x0, x1, y0, y1;
     uint32_t W, H, D;
-    uint32_t reserved; /* must be 0 */
+    uint32_t set;   /* ASK_SET_MANDELBROT or ASK_SET_JULIA */
+    double cr, ci;  /* ASK_SET_JULIA: the fixed c; ignored otherwise */
 } ask_window;
 
 /* Execution form of a subdivision render. */

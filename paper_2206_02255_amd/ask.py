@@ -31,7 +31,8 @@ class AskError(RuntimeError):
 
 class ask_window(C.Structure):
     _fields_ = [("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
-                ("W", C.c_uint32), ("H", C.c_uint32), ("D", C.c_uint32), ("reserved", C.c_uint32)]
+                ("W", C.c_uint32), ("H", C.c_uint32), ("D", C.c_uint32), ("set", C.c_uint32),
+                ("cr", C.c_double), ("ci", C.c_double)]
 
 
 class ask_params(C.Structure):
@@ -107,10 +108,19 @@ def status_str(s):
     return lib.ask_status_str(s).decode()
 
 
+SET_MANDELBROT, SET_JULIA = 0, 1
+
+
 def window(w):
-    """ask_window from any object with x0, x1, y0, y1, W, H, D."""
+    """ask_window from any object with x0, x1, y0, y1, W, H, D and optionally
+    julia: None (the Mandelbrot set) or the fixed c (cr, ci) of a filled
+    Julia set."""
+    j = getattr(w, "julia", None)
+    if j is None:
+        return ask_window(float(w.x0), float(w.x1), float(w.y0), float(w.y1),
+                          int(w.W), int(w.H), int(w.D), SET_MANDELBROT, 0.0, 0.0)
     return ask_window(float(w.x0), float(w.x1), float(w.y0), float(w.y1),
-                      int(w.W), int(w.H), int(w.D), 0)
+                      int(w.W), int(w.H), int(w.D), SET_JULIA, float(j[0]), float(j[1]))
 
 
 def params(g, r, B, form="levels"):

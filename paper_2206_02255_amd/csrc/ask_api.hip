@@ -100,7 +100,11 @@ ask_status check_window(const ask_window *w) {
         return ASK_EINVAL;
     if (w->W < 1 || w->H < 1 || w->W > 65536 || w->H > 65536)
         return ASK_EINVAL;
-    if (w->D < 1 || w->D > 0x7fffffffu || w->reserved != 0)
+    if (w->D < 1 || w->D > 0x7fffffffu)
+        return ASK_EINVAL;
+    if (w->set != ASK_SET_MANDELBROT && w->set != ASK_SET_JULIA)
+        return ASK_EINVAL;
+    if (w->set == ASK_SET_JULIA && (!std::isfinite(w->cr) || !std::isfinite(w->ci)))
         return ASK_EINVAL;
     return ASK_OK;
 }
@@ -184,6 +188,9 @@ Image make_image(const ask_window *w, const ask_params *p, uint32_t *out) {
     im.g = p ? p->g : 1;
     im.r = p ? p->r : 2;
     im.B = p ? p->B : 1;
+    im.julia = w->set == ASK_SET_JULIA ? 1u : 0u;
+    im.jr = im.julia ? w->cr : 0.0;
+    im.ji = im.julia ? w->ci : 0.0;
     im.out = out;
     return im;
 }

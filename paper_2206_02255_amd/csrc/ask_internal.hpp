@@ -14,8 +14,12 @@ constexpr int kMaxLevels = 64;
 // Per-image constants, computed on the host (the device never divides).
 struct Image {
     double cxm, cym, hx, hy;  // pixel centre = (cxm + (2px+1-W) hx, cym + (2py+1-H) hy)
+    double jr, ji;            // julia: the fixed c
     uint32_t W, H, D;
     uint32_t g, r, B;         // initial grid, split factor and stop size
+    uint32_t julia;           // 0: the pixel's point is c, z_0 = 0 (Mandelbrot);
+                              // 1: the pixel's point is z_0, c = (jr, ji) (filled Julia set)
+    uint32_t pad_;
     uint32_t *out;            // W*H dwell image, row-major, row 0 on the y0 side
 };
 

@@ -25,6 +25,19 @@ __device__ __forceinline__ void pixel_c(const Image &im, uint32_t px, uint32_t p
     ci = im.cym + ty;
 }
 
+// The orbit start of pixel (px, py): z_0 and c. Mandelbrot set: z_0 = 0 and
+// c is the pixel's point; filled Julia set: z_0 is the pixel's point and c
+// the image's fixed constant.
+__device__ __forceinline__ void pixel_orbit(const Image &im, uint32_t px, uint32_t py,
+                                            double &zr, double &zi, double &cr, double &ci) {
+    double pr, pi;
+    pixel_c(im, px, py, pr, pi);
+    zr = im.julia ? pr : 0.0;
+    zi = im.julia ? pi : 0.0;
+    cr = im.julia ? im.jr : pr;
+    ci = im.julia ? im.ji : pi;
+}
+
 // ---------------------------------------------------------------------------
 // Dwell (Sec. 6): first k >= 1 with |z_k|^2 > 4, z_0 = 0, z_k = z_{k-1}^2 + c,
 // or D. One iteration is 3 multiplies and 4 adds, and the test reuses the
@@ -58,8 +71,10 @@ constexpr uint32_t kStride = 16;
 // inside it. A failing test restarts the stretch from its saved start with a
 // test after every iteration, which finds the same first k as the plain loop.
 // Other c (|c| near or above 2, NaN) take the plain loop from the start.
-__device__ __forceinline__ uint32_t dwell(double cr, double ci, uint32_t D) {
-    double zr = 0.0, zi = 0.0, zr2 = 0.0, zi2 = 0.0;
+// The orbit starts at z_0 = (zr, zi): 0 for the Mandelbrot set, the pixel's
+// point for a filled Julia set; the growth argument does not depend on z_0.
+__device__ __forceinline__ uint32_t dwell(double zr, double zi, double cr, double ci, uint32_t D) {
+    double zr2 = zr * zr, zi2 = zi * zi;
     uint32_t k = 0;
     if (cr * cr + ci * ci <= 3.99) {
         while (k + kStride <= D) {
@@ -177,9 +192,9 @@ __global__ __launch_bounds__(kBlock) void exhaustive_kernel(Image im) {
     const uint32_t py = blockIdx.y * 16 + wave * 4 + (lane >> 4);
     if (px >= im.W || py >= im.H)
         return;
-    double cr, ci;
-    pixel_c(im, px, py, cr, ci);
-    put_dwell(im.out, (size_t)py * im.W + px, dwell(cr, ci, im.D));
+    double zr, zi, cr, ci;
+    pixel_orbit(im, px, py, zr, zi, cr, ci);
+    put_dwell(im.out, (size_t)py * im.W + px, dwell(zr, zi, cr, ci, im.D));
 }
 
 
@@ -245,9 +260,10 @@ __device__ __forceinline__ bool dwell_stream(const Image &im, uint32_t n, PixelO
                 const uint32_t j = next + lane_rank(idle);
                 if (j < n && pixel_of(j, px, py)) {
                     have = true;
-                    pixel_c(im, px, py, cr, ci);
+                    pixel_orbit(im, px, py, zr, zi, cr, ci);
                     special = !(cr * cr + ci * ci <= 3.99);
-                    zr = zi = zr2 = zi2 = 0.0;
+                    zr2 = zr * zr;
+                    zi2 = zi * zi;
                     kbase = 0;
                 }
             }
@@ -426,6 +442,9 @@ __device__ __forceinline__ Image image_of(const SubdivArgs &a, uint32_t img) {
         im.g = t.g;
         im.r = t.r;
         im.B = t.B;
+        im.jr = t.jr;
+        im.ji = t.ji;
+        im.julia = t.julia;
         im.out = t.out;
         return im;
     }

@@ -55,7 +55,7 @@ def test_validation(ask):
               Window(-1, 1, -1, 1, 8, 65537, 10), Window(-1, 1, -1, 1, 8, 8, 2**31)]:
         assert ask.ask_validate(ask.window(w)) == ask.EINVAL
     bad = ask.window(Window(-1, 1, -1, 1, 8, 8, 10))
-    bad.reserved = 1
+    bad.set = 2
     assert ask.ask_validate(bad) == ask.EINVAL
 
 
@@ -81,3 +81,34 @@ def test_create_without_device_reports_device_error(ask):
     with pytest.raises(ask.AskError) as e:
         ask.ask_create(0)
     assert e.value.status == ask.EDEVICE
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes structures of the binding have the header's sizes and field
+    offsets (compiled with the host C compiler from include/ask.h)."""
+    import ctypes
+    import subprocess
+
+    from paper_2206_02255_amd import ask
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    fields = {"ask_window": [f for f, _ in ask.ask_window._fields_],
+              "ask_params": [f for f, _ in ask.ask_params._fields_],
+              "ask_server_cfg": [f for f, _ in ask.ask_server_cfg._fields_]}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ask.h"', 'int main(void) {']
+    for s, fs in fields.items():
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (s, s))
+        for f in fs:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (s, f, s, f))
+    lines.append('return 0; }')
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                 check=True).stdout.splitlines())
+    for s, fs in fields.items():
+        cls = getattr(ask, s)
+        assert int(got[s]) == ctypes.sizeof(cls), s
+        for f in fs:
+            assert int(got["%s.%s" % (s, f)]) == getattr(cls, f).offset, (s, f)

@@ -141,6 +141,14 @@ def deep_window(seed=3, n=32768, D=8192, width=1e-6):
 # MI355X (near the boundary few regions are uniform, so wider leaves pay).
 DEEP_PARAMS = Params(64, 2, 64)
 
+# The second escape-time workload of the class: the filled Julia set of
+# c = -1 (the basilica), whose interior is large and bounded by a thin
+# boundary, over the square |Re z0|, |Im z0| <= 1.7 that holds it, at the
+# single-image size and dwell limit of the Mandelbrot window.
+JULIA_C = (-1.0, 0.0)
+JULIA = Window(-1.7, 1.7, -1.7, 1.7, 16384, 16384, 2048, julia=JULIA_C)
+JULIA_PARAMS = Params(64, 4, 16)
+
 
 def batch_params(side):
     """(g, r, B) for a batch or serving image of the given side: level-0
