@@ -78,6 +78,7 @@ def parse():
                     help="images of the batched workload (0: skip it)")
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--no-deep", action="store_true", help="skip the deep-zoom image")
+    ap.add_argument("--no-julia", action="store_true", help="skip the Julia-set image")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first copy BYTES of device memory once (a plain copy kernel of known "
                          "size, to scale the memory-traffic counters of a profile)")
@@ -178,6 +179,55 @@ def deep_leg(ctx, torch, ask, workloads, sp):
     ask.ask_enable_timing(ctx, False)
     ask.ask_synchronize(ctx, sp)
     del out, ex
+    return res
+
+
+def julia_leg(ctx, torch, ask, workloads, sp, steps):
+    """The filled Julia set of c = -1 at 16384^2, D = 2048 (the second
+    escape-time workload of the class): exhaustive kernel, persistent and
+    per-level subdivision with the single-image parameters."""
+    w, p = workloads.JULIA, workloads.JULIA_PARAMS
+    win = ask.window(w)
+    out = torch.empty(w.W * w.H, dtype=torch.int32, device="cuda")
+    log("julia: %s, exhaustive" % (w,))
+    ask.ask_enable_timing(ctx, True)
+    ask.ask_dwell_exhaustive(ctx, win, out.data_ptr(), sp)
+    ex_ms = []
+    for _ in range(3):
+        ask.ask_dwell_exhaustive(ctx, win, out.data_ptr(), sp)
+        ex_ms.append(ask.ask_last_kernel_ms(ctx))
+    ex_ms = min(ex_ms)
+    ex_iters = int(out.to(torch.int64).sum().item())
+    ex = out.clone()
+    res = {"workload": "julia-basilica-16384x16384-D2048", "c": list(w.julia),
+           "window": [w.x0, w.x1, w.y0, w.y1], "g": p.g, "r": p.r, "B": p.B,
+           "exhaustive": {"kernel_ms": round(ex_ms, 3), "dwell_iterations": ex_iters,
+                          "fp64_frac": round(FLOPS_PER_ITERATION * ex_iters / (ex_ms * 1e-3) / 1e12
+                                             / PEAK_FP64_TFLOPS, 4)}}
+    images = {}
+    for form in ("persistent", "levels"):
+        log("julia: %s" % form)
+        prm = ask.params(p.g, p.r, p.B, form)
+        st = ask.ask_dwell_subdiv(ctx, win, prm, out.data_ptr(), sp, want_stats=True)
+        iters = st["iters_ring"] + st["iters_leaf"]
+        ms = []
+        for _ in range(max(3, steps)):
+            ask.ask_dwell_subdiv(ctx, win, prm, out.data_ptr(), sp)
+            ms.append(ask.ask_last_kernel_ms(ctx))
+        ms.sort()
+        med = ms[len(ms) // 2]
+        res[form] = {"kernel_ms": round(med, 3), "dwell_iterations": iters,
+                     "mpix_s": round(w.pixels / (med * 1e-3) / 1e6, 1),
+                     "fp64_frac": round(FLOPS_PER_ITERATION * iters / (med * 1e-3) / 1e12
+                                        / PEAK_FP64_TFLOPS, 4),
+                     "speedup_vs_exhaustive": round(ex_ms / med, 2),
+                     "work_reduction": round(ex_iters / iters, 2),
+                     "pixels_differing_from_exhaustive": int((out != ex).sum().item())}
+        images[form] = out.clone()
+    res["levels_equals_persistent"] = bool(torch.equal(images["levels"], images["persistent"]))
+    ask.ask_enable_timing(ctx, False)
+    ask.ask_synchronize(ctx, sp)
+    del out, ex, images
     return res
 
 
@@ -327,6 +377,8 @@ def main():
         result["forms"]["served"] = served_leg(ctx, ask, workloads, args.serve_seconds)
     if not args.no_deep:
         result["forms"]["deep"] = deep_leg(ctx, torch, ask, workloads, sp)
+    if not args.no_julia:
+        result["forms"]["julia"] = julia_leg(ctx, torch, ask, workloads, sp, args.steps)
 
     if not args.no_cpu_baseline:
         import numpy as np

@@ -292,6 +292,10 @@ __device__ __forceinline__ bool dwell_stream(const Image &im, uint32_t n, PixelO
                         zi2 = zi * zi;
                     }
                     if (!(zr2 + zi2 <= 4.0)) {
+                        // Escapes are rare: an empty asm keeps the restore
+                        // on a branch, so the common stretch does not pay
+                        // a select per register of the state.
+                        asm volatile("");
                         zr = szr;
                         zi = szi;
                         zr2 = szr2;
