@@ -89,13 +89,25 @@ typedef enum ask_form {
     ASK_FORM_PERSISTENT = 2
 } ask_form;
 
+/* Leaf work in the persistent form (and in serving): how many waves share
+ * one region's per-pixel work (Sec. 4.3, one block per region, SBR, against
+ * several blocks per region, MBR). A leaf of more than `band` pixels is
+ * queued as row bands of about `band` pixels that any wave may take (MBR);
+ * smaller leaves, and every leaf with ASK_BAND_NONE, are computed whole by
+ * the wave that decided them (SBR). 0 selects ASK_BAND_DEFAULT. The
+ * per-level forms always compute leaves whole. */
+#define ASK_BAND_DEFAULT 1024u
+#define ASK_BAND_NONE 0xffffffffu
+
 /* Subdivision parameters (Sec. 4.2.1, 6.2): an initial g x g grid of
  * regions, r x r splits, stop size B (a region with both sides <= B whose
  * border is not uniform is computed per pixel). Valid: 1 <= g <= min(W, H),
- * 2 <= r <= 1024, 1 <= B <= 65536. form: an ask_form. */
+ * 2 <= r <= 1024, 1 <= B <= 65536. form: an ask_form. band: 0,
+ * ASK_BAND_NONE, or 64 <= band <= 2^24 (see above). */
 typedef struct ask_params {
     uint32_t g, r, B;
     uint32_t form;
+    uint32_t band;
 } ask_params;
 
 /* Work counters of a render, filled when the caller asks for them. */

@@ -36,7 +36,8 @@ class ask_window(C.Structure):
 
 
 class ask_params(C.Structure):
-    _fields_ = [("g", C.c_uint32), ("r", C.c_uint32), ("B", C.c_uint32), ("form", C.c_uint32)]
+    _fields_ = [("g", C.c_uint32), ("r", C.c_uint32), ("B", C.c_uint32), ("form", C.c_uint32),
+                ("band", C.c_uint32)]
 
 
 class ask_server_cfg(C.Structure):
@@ -123,8 +124,15 @@ def window(w):
                       int(w.W), int(w.H), int(w.D), SET_JULIA, float(j[0]), float(j[1]))
 
 
-def params(g, r, B, form="levels"):
-    return ask_params(int(g), int(r), int(B), FORMS[form] if isinstance(form, str) else int(form))
+BAND_DEFAULT, BAND_NONE = 1024, 0xffffffff
+
+
+def params(g, r, B, form="levels", band=0):
+    """ask_params; band: pixels per queued leaf band in the persistent form and
+    in serving (0: BAND_DEFAULT; BAND_NONE: every leaf computed whole by the
+    wave that decides it)."""
+    return ask_params(int(g), int(r), int(B), FORMS[form] if isinstance(form, str) else int(form),
+                      int(band))
 
 
 def _check(s, ctx=None):

@@ -10,7 +10,10 @@ the GPU:
   the split cost lambda (S = lambda A) and the seconds per model time unit,
   with P the measured split probability and q = CUs, c = 64 lanes;
 * ``tune`` returns the measured optimum and the model optimum, and caches the
-  measured choice in a JSON file keyed by the workload class.
+  measured choice in a JSON file keyed by the workload class;
+* ``compare_schemes`` measures one region per wave for leaf work (SBR, Sec.
+  4.3.1) against leaves shared by several waves as row bands (MBR, Sec.
+  4.3.2) at several band sizes, beside the model's T_MBR / T_SBR.
 
 Run ``python -m paper_2206_02255_amd.autotune --size 16384 --dwell 2048`` for
 the sweep of the paper's window.
@@ -71,6 +74,44 @@ def sweep(ctx, win, grid, form="persistent", reps=3, out=None):
         ask.ask_enable_timing(ctx, False)
         ask.ask_synchronize(ctx, stream)
     return rows
+
+
+def compare_schemes(ctx, win, g, r, B, bands=(ask.BAND_NONE, 4096, 1024, 256), reps=5, q=256,
+                    c=64, lam=1.0):
+    """Persistent render of ``win`` with (g, r, B) for every leaf band size of
+    ``bands`` (ask.BAND_NONE: SBR, each leaf on the wave that decides it;
+    others: MBR, leaves above that many pixels shared out as row bands). Returns
+    the measured kernel times (best and median of ``reps``) and the cost
+    model's T_SBR and T_MBR for the same parameters, with P measured here."""
+    import torch
+    stream = torch.cuda.current_stream().cuda_stream
+    out = torch.empty(win.W * win.H, dtype=torch.int32, device="cuda")
+    ask.ask_enable_timing(ctx, True)
+    rows = []
+    P = None
+    try:
+        for band in bands:
+            prm = ask.params(g, r, B, "persistent", band)
+            st = ask.ask_dwell_subdiv(ctx, win, prm, out.data_ptr(), stream, want_stats=True)
+            P = costmodel.split_probability(st)
+            ms = []
+            for _ in range(reps):
+                ask.ask_dwell_subdiv(ctx, win, prm, out.data_ptr(), stream)
+                ms.append(ask.ask_last_kernel_ms(ctx))
+            ms.sort()
+            rows.append({"band": "none (SBR)" if band == ask.BAND_NONE else int(band),
+                         "best_ms": ms[0], "median_ms": ms[len(ms) // 2]})
+    finally:
+        ask.ask_enable_timing(ctx, False)
+        ask.ask_synchronize(ctx, stream)
+    n, A = float(max(win.W, win.H)), float(win.D)
+    t_sbr = float(costmodel.time_sbr(n, g, r, B, A, P, lam, q, c))
+    t_mbr = float(costmodel.time_mbr(n, g, r, B, A, P, lam, q, c))
+    sbr = rows[0]["best_ms"] if bands[0] == ask.BAND_NONE else None
+    best_mbr = min((row["best_ms"] for row in rows if row["band"] != "none (SBR)"), default=None)
+    return {"g": g, "r": r, "B": B, "P": P, "lambda": lam, "rows": rows,
+            "model": {"T_SBR": t_sbr, "T_MBR": t_mbr, "T_MBR/T_SBR": t_mbr / t_sbr},
+            "measured": {"best_MBR/SBR": (best_mbr / sbr) if sbr and best_mbr else None}}
 
 
 def fit_model(rows, n, A, q, c=64, lambdas=None):
@@ -156,9 +197,33 @@ def main(argv=None):
     ap.add_argument("--grid", default="paper", choices=["paper", "wide"])
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--json", default=None, help="write the result here")
+    ap.add_argument("--schemes", default=None, metavar="G,R,B",
+                    help="compare SBR and MBR leaf work for these parameters instead")
+    ap.add_argument("--window", default="paper", choices=["paper", "deep", "julia"],
+                    help="--schemes: the paper's window (--size, --dwell), the deep zoom "
+                         "or the Julia-set workload")
     args = ap.parse_args(argv)
+    import workloads
     from workloads import LARGE_SWEEP, paper_window
-    w = paper_window(args.size, args.dwell)
+    w = {"paper": lambda: paper_window(args.size, args.dwell), "deep": workloads.deep_window,
+         "julia": lambda: workloads.JULIA}[args.window]()
+    if args.schemes:
+        g, r, B = (int(x) for x in args.schemes.split(","))
+        ctx = ask.ask_create(0)
+        try:
+            props = torch.cuda.get_device_properties(0)
+            res = compare_schemes(ctx, ask.window(w), g, r, B, reps=args.reps,
+                                  q=props.multi_processor_count)
+        finally:
+            ask.ask_destroy(ctx)
+        for row in res["rows"]:
+            print("band %-12s best %8.3f ms  median %8.3f ms" %
+                  (row["band"], row["best_ms"], row["median_ms"]), flush=True)
+        print(json.dumps({k: res[k] for k in ("g", "r", "B", "P", "model", "measured")}))
+        if args.json:
+            with open(args.json, "w") as f:
+                json.dump(res, f, indent=1)
+        return
     grid = ([(p.g, p.r, p.B) for p in LARGE_SWEEP] if args.grid == "paper"
             else default_grid(args.size))
     ctx = ask.ask_create(0)

@@ -116,6 +116,8 @@ ask_status check_params(const ask_window *w, const ask_params *p) {
         return ASK_EINVAL;
     if (p->r < 2 || p->r > 1024 || p->B < 1 || p->B > 65536)
         return ASK_EINVAL;
+    if (p->band != 0 && p->band != ASK_BAND_NONE && (p->band < 64 || p->band > (1u << 24)))
+        return ASK_EINVAL;
     if (p->form > ASK_FORM_PERSISTENT)
         return ASK_EINVAL;
     return ASK_OK;
@@ -152,6 +154,7 @@ uint64_t level_bound(uint64_t pixels, uint32_t g, uint32_t r, uint32_t lv) {
 struct Bounds {
     std::vector<uint64_t> level = std::vector<uint64_t>(kMaxLevels, 0);  // regions per level
     uint64_t pixels = 0;
+    uint32_t band = ASK_BAND_NONE;  // smallest leaf band of the images
     uint64_t regions() const {
         uint64_t t = 0;
         for (uint64_t v : level)
@@ -160,8 +163,10 @@ struct Bounds {
     }
     // Queue entries when leaves are queued as bands of `band` pixels: the
     // regions, and the bands, of which every one but a leaf's last has at
-    // least band / 2 pixels.
-    uint64_t queue_entries(uint32_t band) const { return pixels / (band / 2) + 2 * regions(); }
+    // least band / 2 pixels (none when no leaf is banded).
+    uint64_t queue_entries() const {
+        return (band == ASK_BAND_NONE ? 0 : pixels / (band / 2)) + 2 * regions();
+    }
 };
 
 // Add one image's bounds to b; returns its level count.
@@ -171,6 +176,7 @@ uint32_t add_bounds(const Image &im, Bounds &b) {
     for (uint32_t lv = 0; lv < lv_i && lv < (uint32_t)kMaxLevels; ++lv)
         b.level[lv] += level_bound(pixels, im.g, im.r, lv);
     b.pixels += pixels;
+    b.band = std::min(b.band, im.band);
     return lv_i;
 }
 
@@ -188,6 +194,7 @@ Image make_image(const ask_window *w, const ask_params *p, uint32_t *out) {
     im.g = p ? p->g : 1;
     im.r = p ? p->r : 2;
     im.B = p ? p->B : 1;
+    im.band = p && p->band ? p->band : kLeafTask;
     im.julia = w->set == ASK_SET_JULIA ? 1u : 0u;
     im.jr = im.julia ? w->cr : 0.0;
     im.ji = im.julia ? w->ci : 0.0;
@@ -482,7 +489,7 @@ ask_status render(ask_ctx *ctx, const Image *ims, uint32_t n, uint32_t form, hip
     uint64_t widest = 0;
     for (uint32_t lv = 0; lv < levels; ++lv)
         widest = std::max(widest, bound[lv]);
-    const uint64_t need = form == ASK_FORM_PERSISTENT ? b.queue_entries(kLeafTask) : widest;
+    const uint64_t need = form == ASK_FORM_PERSISTENT ? b.queue_entries() : widest;
     const uint64_t want = std::min<uint64_t>(need, kQueueBudget);
     const bool may_overflow = need > want;
     if (capturing && (may_overflow || (form == ASK_FORM_PERSISTENT ? ctx->queue_cap < want
@@ -582,8 +589,6 @@ ask_status render(ask_ctx *ctx, const Image *ims, uint32_t n, uint32_t form, hip
         }
         a.queue = ctx->queue;
         a.cap = (uint32_t)std::min<size_t>(ctx->queue_cap, 0xffffffffu - 65536u);
-        a.leaf_band = kLeafTask;
-        a.leaf_min = kLeafTask;
         a.epoch = epoch;
         a.wait_ticks = (uint64_t)(ctx->wait_limit_s * ctx->clock_hz);
         e = launch_seed_queue(a, (uint32_t)nseeds, s);
@@ -950,7 +955,7 @@ ask_status ask_server_submit(ask_server *sv, const ask_window *win, const ask_pa
     Bounds b;
     if (add_bounds(im, b) > (uint32_t)kMaxLevels - 1)
         return fail(ctx, ASK_EINVAL, "too many levels%s", nullptr);
-    const uint64_t qlen = b.queue_entries(kLeafTask);
+    const uint64_t qlen = b.queue_entries();
     if (qlen > sv->queue_entries)
         return fail(ctx, ASK_ENOMEM, "the request's worst case exceeds the server pool%s", nullptr);
     DeviceGuard guard(ctx->device);

@@ -19,7 +19,8 @@ struct Image {
     uint32_t g, r, B;         // initial grid, split factor and stop size
     uint32_t julia;           // 0: the pixel's point is c, z_0 = 0 (Mandelbrot);
                               // 1: the pixel's point is z_0, c = (jr, ji) (filled Julia set)
-    uint32_t pad_;
+    uint32_t band;            // queue forms: leaves above band pixels go out as row bands
+                              // of about band pixels; others are computed whole
     uint32_t *out;            // W*H dwell image, row-major, row 0 on the y0 side
 };
 
@@ -37,10 +38,11 @@ struct Region {
 // a band of a leaf whose pixels are all computed.
 enum Kind : uint32_t { kScan = 0, kLeaf = 1 };
 
-// Leaf bands of the queue forms: leaves above kLeafTask pixels are queued as
-// bands of about kLeafTask pixels, each computed by the wave that takes it,
-// so that no wave holds a whole large leaf while others idle.
-constexpr uint32_t kLeafTask = 1024;
+// Leaf bands of the queue forms, by default: leaves above kLeafTask pixels
+// are queued as bands of about kLeafTask pixels, each computed by the wave
+// that takes it, so that no wave holds a whole large leaf while others idle.
+// An image's band size can be set per render (Image::band).
+constexpr uint32_t kLeafTask = ASK_BAND_DEFAULT;
 
 // Launch epoch of persistent renders captured in a graph (whose queue is
 // cleared by the graph itself); other renders cycle through 1 .. kGraphEpoch - 1.
@@ -90,9 +92,6 @@ struct SubdivArgs {
     Region *out;                // level kernels: regions of the next level
     Region *queue;              // persistent kernel: the region queue
     uint32_t cap;               // capacity (entries) of out / queue
-    uint32_t leaf_band;         // queue forms: pixels per leaf band
-    uint32_t leaf_min;          // queue forms: leaves above this many pixels are queued as
-                                // bands, smaller ones computed by the wave that decides them
     uint32_t epoch;
     uint64_t wait_ticks;        // persistent kernel: longest wait, constant-clock ticks
     uint32_t *ctrl;

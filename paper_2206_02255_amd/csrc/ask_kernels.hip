@@ -449,6 +449,7 @@ __device__ __forceinline__ Image image_of(const SubdivArgs &a, uint32_t img) {
         im.jr = t.jr;
         im.ji = t.ji;
         im.julia = t.julia;
+        im.band = t.band;
         im.out = t.out;
         return im;
     }
@@ -519,10 +520,11 @@ __device__ void split_region(const SubdivArgs &a, uint32_t img, uint32_t x, uint
 }
 
 // Queue forms: the per-pixel work of a leaf becomes row bands of about
-// a.leaf_band pixels, queued as leaf entries that any wave can take.
+// `band` pixels, queued as leaf entries that any wave can take.
 __device__ void queue_leaf_bands(const SubdivArgs &a, uint32_t img, uint32_t x, uint32_t y,
-                                 uint32_t w, uint32_t h, uint32_t level, uint32_t lane) {
-    const uint32_t hb = max(1u, a.leaf_band / w);
+                                 uint32_t w, uint32_t h, uint32_t band, uint32_t level,
+                                 uint32_t lane) {
+    const uint32_t hb = max(1u, band / w);
     const uint32_t nb = (h + hb - 1) / hb;
     emit_entries<true>(a, a.queue, &a.ctrl[kTail], a.cap, nb, kLeaf, level, lane,
                        [&](uint32_t j, Region &e) {
@@ -554,8 +556,8 @@ __device__ void decide_region(const SubdivArgs &a, uint32_t img, const Image &im
     if (w <= im.B && h <= im.B) {
         if (st)
             wave_add64(&st->leaves[level], 1ull);
-        if (kQueue && w * h > a.leaf_min) {
-            queue_leaf_bands(a, img, x, y, w, h, level, lane);
+        if (kQueue && w * h > im.band) {
+            queue_leaf_bands(a, img, x, y, w, h, im.band, level, lane);
             return;
         }
         unsigned long long li = leaf_region(im, x, y, w, h);
@@ -773,8 +775,6 @@ __device__ __forceinline__ SubdivArgs slot_args(const ServerArgs &sa, ServerSlot
     a.epoch = gen;
     a.wait_ticks = sa.wait_ticks;
     a.ctrl = sl->ctrl;
-    a.leaf_band = kLeafTask;
-    a.leaf_min = kLeafTask;
     return a;
 }
 

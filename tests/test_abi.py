@@ -50,6 +50,10 @@ def test_validation(ask):
     for g, r, B in [(0, 2, 8), (49, 2, 8), (4, 1, 8), (4, 1025, 8), (4, 2, 0)]:
         assert ask.ask_validate(good, ask.params(g, r, B)) == ask.EINVAL
     assert ask.ask_validate(good, ask.params(4, 2, 8, form=7)) == ask.EINVAL
+    for band in (0, 64, 1000, 1 << 24, ask.BAND_NONE):
+        assert ask.ask_validate(good, ask.params(4, 2, 8, "persistent", band)) == 0
+    for band in (1, 63, (1 << 24) + 1):
+        assert ask.ask_validate(good, ask.params(4, 2, 8, "persistent", band)) == ask.EINVAL
     for w in [Window(0.5, -1.5, -1, 1, 8, 8, 10), Window(-1, 1, -1, 1, 0, 8, 10),
               Window(-1, 1, -1, 1, 8, 8, 0), Window(-1, float("inf"), -1, 1, 8, 8, 10),
               Window(-1, 1, -1, 1, 8, 65537, 10), Window(-1, 1, -1, 1, 8, 8, 2**31)]:

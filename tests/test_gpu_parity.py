@@ -295,3 +295,22 @@ def test_persistent_wait_limit_reports_timeout(gpu, ref):
     img, _ = gpu_subdiv(gpu, w, 2, 2, 8, "persistent")
     assert np.array_equal(img, ref.subdiv(w, 2, 2, 8)[0])
     ask.ask_synchronize(ctx, stream)
+
+
+@pytest.mark.parametrize("band", [0xffffffff, 64, 200, 4096])
+def test_persistent_leaf_bands(gpu, ref, band):
+    """Leaf work shared by several waves (row bands of `band` pixels) or kept
+    on the deciding wave (0xffffffff): the same image and counters."""
+    ask, ctx, torch = gpu
+    cases = [(Window(-1.5, 0.5, -1.0, 1.0, 600, 517, 700), 4, 2, 128),
+             (Window(-0.75, -0.73, 0.1, 0.12, 400, 300, 3000), 2, 3, 200),
+             (Window(-1.6, 1.6, -1.6, 1.6, 512, 512, 400, julia=(-1.0, 0.0)), 8, 2, 64)]
+    for w, g, r, B in cases:
+        print(band, w, (g, r, B), flush=True)
+        out = _out(torch, w)
+        st = ask.ask_dwell_subdiv(ctx, ask.window(w), ask.params(g, r, B, "persistent", band),
+                                  out.data_ptr(), torch.cuda.current_stream().cuda_stream,
+                                  want_stats=True)
+        want, rst = ref.subdiv(w, g, r, B)
+        assert np.array_equal(_host(torch, out, w), want), (w, band)
+        assert_same_stats(st, rst)
