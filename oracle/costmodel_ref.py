@@ -89,3 +89,27 @@ def time_mbr(n, g, r, B, A, P, lam, q, c):
         total += math.ceil(float(n) * n * P ** i * (1.0 - P) / (q * c))
     total += A * math.ceil(float(n) * n / (q * c)) * P ** (t - 1)
     return total
+
+
+def time_sbr_levels(n, g, r, B, A, P, lam, q, c, sigma=0.0, levels=None):
+    """T_SBR of Sec. 4.3.1 in its general form: a split probability P_i per
+    level (a list; level i's expected region count is G R^i prod_{j<i} P_j,
+    Sec. 4.2, without assumption i) and a cost sigma that every region adds
+    on its block beyond the paper's terms (taking the region from the queue
+    and publishing its outcome), in the same units as the other terms, over
+    tau levels as printed or the given number of levels. With one P for every
+    level, sigma = 0 and tau as printed this is time_sbr."""
+    t = tau(n, g, r, B) if levels is None else levels
+    G, R = g * g, r * r
+    Ps = _probs(P, t)
+    total = 0.0
+    reach = 1.0  # prod_{j<i} P_j
+    for i in range(t - 1):
+        per_region = (math.ceil(4.0 * n / (g * r ** i * c)) * A + Ps[i] * lam * A
+                      + (1.0 - Ps[i]) * math.ceil(float(n) * n / (G * R ** i * c)) + sigma)
+        total += per_region * math.ceil(G * R ** i / q) * reach
+        reach *= Ps[i]
+    last = t - 1
+    total += ((A * math.ceil(float(n) * n / (G * R ** last * c)) + sigma)
+              * math.ceil(G * R ** last / q) * reach)
+    return total

@@ -11,6 +11,11 @@ the GPU:
   with P the measured split probability and q = CUs, c = 64 lanes;
 * ``tune`` returns the measured optimum and the model optimum, and caches the
   measured choice in a JSON file keyed by the workload class;
+* ``fit_model_v2`` and ``guided_search``: the model with measured GPU
+  overheads (a split probability per level, read as a function of the
+  region side, and a per-region scheduling cost sigma) fitted to a few
+  pilot renders, then used as a prior: only the parameters it ranks best
+  are measured;
 * ``compare_schemes`` measures one region per wave for leaf work (SBR, Sec.
   4.3.1) against leaves shared by several waves as row bands (MBR, Sec.
   4.3.2) at several band sizes, beside the model's T_MBR / T_SBR.
@@ -69,6 +74,7 @@ def sweep(ctx, win, grid, form="persistent", reps=3, out=None):
             rows.append({"g": g, "r": r, "B": B, "ms": best,
                          "iterations": st["iters_ring"] + st["iters_leaf"],
                          "P": costmodel.split_probability(st),
+                         "P_levels": costmodel.split_probabilities(st),
                          "regions": sum(st["regions"]), "levels": st["levels"]})
     finally:
         ask.ask_enable_timing(ctx, False)
@@ -136,6 +142,58 @@ def fit_model(rows, n, A, q, c=64, lambdas=None):
     return best
 
 
+def fit_model_v2(rows, n, A, q, c=64, lambdas=None, sigmas=None):
+    """Fit lambda, sigma and the seconds per model unit (kappa) to measured
+    rows (each with its own per-level P_levels, over the levels the render
+    has), least squares in log time.
+    Returns (lambda, sigma, kappa, relative rms error)."""
+    lambdas = np.geomspace(0.01, 1e5, 36) if lambdas is None else lambdas
+    sigmas = np.concatenate(([0.0], np.geomspace(1.0, 1e8, 33))) if sigmas is None else sigmas
+    y = np.log([row["ms"] for row in rows])
+    levels = [costmodel.rendered_levels(n, row["g"], row["r"], row["B"]) for row in rows]
+    best = None
+    for lam in lambdas:
+        for sig in sigmas:
+            m = np.log([costmodel.time_sbr_levels(n, row["g"], row["r"], row["B"], A,
+                                                  row["P_levels"] or [0.0], lam, q, c, sig, L)
+                        for row, L in zip(rows, levels)])
+            k = float(np.mean(y - m))
+            err = float(np.sqrt(np.mean((y - m - k) ** 2)))
+            if best is None or err < best[3]:
+                best = (float(lam), float(sig), math.exp(k), err)
+    return best
+
+
+def guided_search(measure, grid, n, A, q, c=64, pilot=8, top=8):
+    """The model as a prior for the search over ``grid``: measure ``pilot``
+    evenly spaced candidates (measure(list of (g, r, B)) -> rows as ``sweep``
+    returns), fit P(side) from their per-level split probabilities and
+    lambda, sigma, kappa from their times, predict every candidate, and
+    measure the ``top`` best predicted ones not yet measured. Returns the
+    measured rows, the best of them, the fit and the predicted order."""
+    grid = [tuple(p) for p in grid]
+    step = max(1, len(grid) // max(1, pilot))
+    first = grid[::step][:pilot]
+    rows = list(measure(first))
+    points = [(s, p) for row in rows
+              for s, p in zip(costmodel.level_sides(
+                  n, row["g"], row["r"], row["B"],
+                  costmodel.rendered_levels(n, row["g"], row["r"], row["B"])), row["P_levels"])]
+    curve = costmodel.split_curve(points) if points else (lambda s: 0.0)
+    lam, sig, kappa, err = fit_model_v2(rows, n, A, q, c)
+    pred = {p: kappa * costmodel.predict_sbr(n, *p, A, curve, lam, q, c, sig) for p in grid}
+    order = sorted(grid, key=lambda p: pred[p])
+    seen = {(row["g"], row["r"], row["B"]) for row in rows}
+    more = [p for p in order if p not in seen][:top]
+    rows += list(measure(more))
+    best = min(rows, key=lambda row: row["ms"])
+    return {"rows": rows, "measured": len(rows), "best": {k: best[k] for k in ("g", "r", "B", "ms")},
+            "fit": {"lambda": lam, "sigma": sig, "seconds_per_unit": kappa * 1e-3,
+                    "log_rms": err},
+            "predicted_order": [list(p) for p in order[:top + pilot]],
+            "predicted_ms": {"%d,%d,%d" % p: pred[p] for p in order[:top + pilot]}}
+
+
 def model_optimum(grid, n, A, P, lam, q, c=64, scheme="sbr"):
     """The (g, r, B) of ``grid`` that the time model ranks fastest."""
     g, r, B = (np.array([p[i] for p in grid], dtype=np.float64) for i in range(3))
@@ -199,6 +257,9 @@ def main(argv=None):
     ap.add_argument("--json", default=None, help="write the result here")
     ap.add_argument("--schemes", default=None, metavar="G,R,B",
                     help="compare SBR and MBR leaf work for these parameters instead")
+    ap.add_argument("--prior", default=None, nargs="+", metavar="PILOT,TOP",
+                    help="also run the model-guided search (PILOT pilot renders, then the TOP "
+                         "best predicted) against the full sweep's measurements, for each pair")
     ap.add_argument("--window", default="paper", choices=["paper", "deep", "julia"],
                     help="--schemes: the paper's window (--size, --dwell), the deep zoom "
                          "or the Julia-set workload")
@@ -234,6 +295,26 @@ def main(argv=None):
     finally:
         ask.ask_destroy(ctx)
     res["paper_optima"] = PAPER_OPTIMA
+    if args.prior:
+        n, A = float(max(w.W, w.H)), float(w.D)
+        q = torch.cuda.get_device_properties(0).multi_processor_count
+        by_p = {(row["g"], row["r"], row["B"]): row for row in res["rows"]}
+        full_best = min(res["rows"], key=lambda row: row["ms"])
+        res["guided"] = []
+        for pair in args.prior:
+            pilot, top = (int(x) for x in pair.split(","))
+            g_res = guided_search(lambda ps: [by_p[tuple(p)] for p in ps], grid, n, A, q,
+                                  pilot=pilot, top=top)
+            res["guided"].append({"pilot": pilot, "top": top, "measured": g_res["measured"],
+                                  "best": g_res["best"], "fit": g_res["fit"],
+                                  "best_over_full_sweep_best": g_res["best"]["ms"] / full_best["ms"],
+                                  "predicted_order": g_res["predicted_order"]})
+        lam2, sig2, kap2, err2 = fit_model_v2(res["rows"], n, A, q)
+        res["full_sweep"] = {"size": len(res["rows"]),
+                             "best": {k: full_best[k] for k in ("g", "r", "B", "ms")}}
+        res["model_v2_fit_all"] = {"lambda": lam2, "sigma": sig2,
+                                   "seconds_per_unit": kap2 * 1e-3, "log_rms": err2}
+        print(json.dumps({k: res[k] for k in ("guided", "full_sweep", "model_v2_fit_all")}))
     for row in sorted(res["rows"], key=lambda row: row["ms"])[:10]:
         print("g=%3d r=%d B=%3d  %8.3f ms  P=%.3f  iterations=%d" %
               (row["g"], row["r"], row["B"], row["ms"], row["P"], row["iterations"]), flush=True)

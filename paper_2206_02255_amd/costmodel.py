@@ -114,3 +114,79 @@ def split_probability(stats):
     ps = [s / max(1, n) for s, n in zip(stats["splits"], stats["regions"]) if n]
     ps = ps[:-1] if len(ps) > 1 else ps
     return float(np.mean(ps)) if ps else 0.0
+
+
+# ---------------------------------------------------------------------------
+# Model with measured GPU overheads: a split probability per level, read from
+# the render's counters or, for parameters not yet rendered, from the split
+# probability as a function of the region side; and a per-region scheduling
+# cost sigma. Evaluated one (g, r, B) at a time.
+# ---------------------------------------------------------------------------
+
+def rendered_levels(n, g, r, B):
+    """The levels a render has: 1 + the number of r-fold splits that take
+    the level-0 side ceil(n / g) down to B or below (the paper's tau as
+    printed counts one fewer; see the stop rule's reading)."""
+    s, levels = -(-int(n) // int(g)), 1
+    while s > B:
+        s = -(-s // int(r))
+        levels += 1
+    return levels
+
+
+def level_sides(n, g, r, B, levels=None):
+    """Region side n / (g r^i) of each model level i (tau as printed, or
+    the given level count)."""
+    t = int(tau(n, g, r, B)) if levels is None else int(levels)
+    return [float(n) / (g * r ** i) for i in range(t)]
+
+
+def split_probabilities(stats):
+    """Measured P_i of every level that can split: splits / regions."""
+    ps = [s / max(1, n) for s, n in zip(stats["splits"], stats["regions"]) if n]
+    return ps[:-1] if len(ps) > 1 else ps
+
+
+def time_sbr_levels(n, g, r, B, A, P, lam, q, c, sigma=0.0, levels=None):
+    """T_SBR (Sec. 4.3.1) with a split probability per level (a sequence;
+    its last value serves deeper levels), a per-region cost sigma in the
+    units of the other terms, and tau as printed or the given level count.
+    One P for every level, sigma = 0 and tau as printed give time_sbr."""
+    t = int(tau(n, g, r, B)) if levels is None else int(levels)
+    Ps = list(np.atleast_1d(np.asarray(P, dtype=np.float64)))
+    Ps = (Ps + [Ps[-1]] * t)[:t]
+    G, R, n = float(g) * g, float(r) * r, float(n)
+    levels = np.arange(t - 1)
+    GRi = G * R ** levels
+    reach = np.concatenate(([1.0], np.cumprod(Ps[:t - 1])))  # prod_{j<i} P_j, i = 0..t-1
+    P_arr = np.asarray(Ps[:t - 1])
+    per_region = (np.ceil(4.0 * n / (g * r ** levels * c)) * A + P_arr * lam * A
+                  + (1.0 - P_arr) * np.ceil(n * n / (GRi * c)) + sigma)
+    total = float(np.sum(per_region * np.ceil(GRi / q) * reach[:t - 1]))
+    GRl = G * R ** (t - 1)
+    total += (A * np.ceil(n * n / (GRl * c)) + sigma) * np.ceil(GRl / q) * reach[t - 1]
+    return float(total)
+
+
+def split_curve(points):
+    """P as a function of the region side, from measured (side, P) pairs:
+    the mean P of each distinct side, linear in log2(side) between them and
+    constant beyond the ends."""
+    by_side = {}
+    for s, p in points:
+        by_side.setdefault(float(s), []).append(float(p))
+    xs = np.log2(np.array(sorted(by_side)))
+    ys = np.array([np.mean(by_side[s]) for s in sorted(by_side)])
+
+    def P(side):
+        return float(np.interp(np.log2(float(side)), xs, ys))
+    return P
+
+
+def predict_sbr(n, g, r, B, A, curve, lam, q, c, sigma=0.0):
+    """time_sbr_levels over the rendered levels, each level's P read from
+    curve(side)."""
+    L = rendered_levels(n, g, r, B)
+    sides = level_sides(n, g, r, B, L)
+    Ps = [curve(s) for s in sides[:-1]] or [0.0]
+    return time_sbr_levels(n, g, r, B, A, Ps, lam, q, c, sigma, L)

@@ -55,3 +55,32 @@ def test_small_sweep_on_gpu(tmp_path, monkeypatch):
         assert again["measured_optimum"] == res["measured_optimum"]  # from the cache
     finally:
         ask.ask_destroy(ctx)
+
+
+def test_guided_search_finds_the_optimum_with_few_renders():
+    # Synthetic measurements from the model with overheads (known lambda,
+    # sigma, kappa and a split probability that grows with the region side):
+    # the prior, fitted on 8 pilot renders, must lead to the grid's optimum
+    # with at most 16 renders of the 60 and recover lambda and sigma.
+    n, A, q = 16384, 2048.0, 256
+    curve = lambda s: min(0.95, 0.1 + 0.15 * np.log2(s / 8.0))  # noqa: E731
+    lam, sig, kappa = 10.0, 1000.0, 2e-7
+    grid = [(g, r, B) for g in (2, 4, 8, 16, 32) for r in (2, 4, 8) for B in (16, 32, 64, 128)]
+
+    def measure(ps):
+        rows = []
+        for g, r, B in ps:
+            L = costmodel.rendered_levels(n, g, r, B)
+            sides = costmodel.level_sides(n, g, r, B, L)
+            Pl = [curve(s) for s in sides[:-1]] or [0.0]
+            ms = kappa * costmodel.time_sbr_levels(n, g, r, B, A, Pl, lam, q, 64, sig, L)
+            rows.append({"g": g, "r": r, "B": B, "ms": ms, "P_levels": Pl})
+        return rows
+
+    truth = min(measure(grid), key=lambda row: row["ms"])
+    res = autotune.guided_search(measure, grid, n, A, q, pilot=8, top=8)
+    assert res["measured"] <= 16
+    assert (res["best"]["g"], res["best"]["r"], res["best"]["B"]) == (truth["g"], truth["r"], truth["B"])
+    assert res["fit"]["lambda"] == pytest.approx(lam, rel=0.5)
+    assert res["fit"]["sigma"] == pytest.approx(sig, rel=0.7)
+    assert res["fit"]["log_rms"] < 0.05

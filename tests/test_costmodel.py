@@ -99,3 +99,83 @@ def test_product_model_broadcasts_over_grids():
 def test_measured_split_probability():
     st = {"regions": [16, 56, 200, 680], "splits": [14, 50, 170, 0]}
     assert cm.split_probability(st) == pytest.approx((14 / 16 + 50 / 56 + 170 / 200) / 3)
+
+
+# --- the model with measured overheads: per-level P_i and a per-region cost sigma ---
+
+@pytest.mark.parametrize("n,g,r,B", GRID[::6])
+@pytest.mark.parametrize("P", [0.0, 0.4, 1.0])
+def test_levels_model_reduces_to_the_paper_model(n, g, r, B, P):
+    # One P for every level and sigma = 0 is the time of Sec. 4.3.1.
+    t1 = ref.time_sbr(n, g, r, B, 2048.0, P, 3.0, 256, 64)
+    assert ref.time_sbr_levels(n, g, r, B, 2048.0, P, 3.0, 256, 64) == pytest.approx(t1, rel=1e-12)
+    t = ref.tau(n, g, r, B)
+    assert ref.time_sbr_levels(n, g, r, B, 2048.0, [P] * t, 3.0, 256, 64) == pytest.approx(t1, rel=1e-12)
+
+
+@pytest.mark.parametrize("n,g,r,B", GRID[::6])
+def test_sigma_is_paid_once_per_region_round(n, g, r, B):
+    # With P = 1 every level is reached, so sigma adds sigma times the number
+    # of block rounds, sum_i ceil(G R^i / q) over the tau levels.
+    q = 256
+    rounds = sum(math.ceil(g * g * (r * r) ** i / q) for i in range(ref.tau(n, g, r, B)))
+    t0 = ref.time_sbr_levels(n, g, r, B, 512.0, 1.0, 2.0, q, 64, sigma=0.0)
+    t1 = ref.time_sbr_levels(n, g, r, B, 512.0, 1.0, 2.0, q, 64, sigma=7.0)
+    assert t1 - t0 == pytest.approx(7.0 * rounds, rel=1e-9)
+
+
+def test_no_split_at_level_zero_ignores_deeper_levels():
+    # P_0 = 0: no region reaches level 1, whatever the deeper P_i.
+    n, g, r, B = 16384, 16, 4, 16
+    a = ref.time_sbr_levels(n, g, r, B, 2048.0, [0.0, 0.1, 0.2, 0.3], 5.0, 256, 64, sigma=9.0)
+    b = ref.time_sbr_levels(n, g, r, B, 2048.0, [0.0, 0.9, 0.8, 0.7], 5.0, 256, 64, sigma=9.0)
+    assert a == b
+    level0 = (math.ceil(4.0 * n / (g * 64)) * 2048.0 + math.ceil(float(n) * n / (g * g * 64)) + 9.0)
+    assert a == pytest.approx(level0 * math.ceil(g * g / 256), rel=1e-12)
+
+
+def test_levels_model_product_matches_the_oracle():
+    rng = np.random.default_rng(7)
+    for n, g, r, B in GRID:
+        t = ref.tau(n, g, r, B)
+        Ps = list(rng.uniform(0, 1, t))
+        sig = float(rng.uniform(0, 1e4))
+        want = ref.time_sbr_levels(n, g, r, B, 1024.0, Ps, 4.0, 256, 64, sigma=sig)
+        got = cm.time_sbr_levels(n, g, r, B, 1024.0, Ps, 4.0, 256, 64, sigma=sig)
+        assert got == pytest.approx(want, rel=1e-12)
+
+
+def test_split_curve_interpolates_in_log_side_and_clamps():
+    P = cm.split_curve([(256, 0.2), (1024, 0.6), (256, 0.4)])
+    assert P(256) == pytest.approx(0.3) and P(1024) == pytest.approx(0.6)
+    assert P(512) == pytest.approx(0.45)  # halfway in log2
+    assert P(64) == pytest.approx(0.3) and P(1 << 20) == pytest.approx(0.6)
+
+
+def test_level_sides_and_probabilities():
+    # tau as printed (log_4(16384 / (64 * 16)) = 2 model levels; the render
+    # itself has a third, 16-pixel level -- the reading of the stop rule)
+    assert cm.level_sides(16384, 64, 4, 16) == [256.0, 64.0]
+    assert cm.level_sides(16384, 16, 2, 32) == [1024.0, 512.0, 256.0, 128.0, 64.0]
+    st = {"splits": [10, 30, 0], "regions": [20, 160, 480]}
+    assert cm.split_probabilities(st) == [0.5, 30 / 160]
+
+
+def test_rendered_levels_match_the_library():
+    # The level count the model uses for measured renders is the one the
+    # library computes for the same parameters (a host call, no GPU).
+    from paper_2206_02255_amd import ask
+    from workloads import Window
+    for n, g, r, B in GRID + [(16384, 64, 4, 16), (16384, 16, 2, 32), (1000, 3, 3, 7)]:
+        w = ask.window(Window(-1.5, 0.5, -1.0, 1.0, n, n, 256))
+        assert cm.rendered_levels(n, g, r, B) == ask.ask_level_count(w, ask.params(g, r, B)), (n, g, r, B)
+
+
+def test_rendered_levels_product_matches_the_oracle():
+    rng = np.random.default_rng(8)
+    for n, g, r, B in GRID[::3]:
+        L = cm.rendered_levels(n, g, r, B)
+        Ps = list(rng.uniform(0, 1, L))
+        want = ref.time_sbr_levels(n, g, r, B, 1024.0, Ps, 4.0, 256, 64, sigma=50.0, levels=L)
+        got = cm.time_sbr_levels(n, g, r, B, 1024.0, Ps, 4.0, 256, 64, sigma=50.0, levels=L)
+        assert got == pytest.approx(want, rel=1e-12)
