@@ -117,21 +117,26 @@ def batched_leg(ctx, torch, ask, workloads, sp, count, steps):
     ask.ask_enable_timing(ctx, False)
     batch_img = out.clone()
 
-    def one_by_one(form):
+    def one_by_one(form, params):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        for w, p, ptr in zip(wins, prms, ptrs):
+        for w, p, ptr in zip(wins, params, ptrs):
             ask.ask_dwell_subdiv(ctx, w, ask.params(p.g, p.r, p.B, form), ptr, sp)
         torch.cuda.synchronize()
         ask.ask_synchronize(ctx, sp)
         return 1e3 * (time.perf_counter() - t)
 
-    seq_pers_ms = one_by_one("persistent")
+    # The same images and parameters one at a time must give the batch's images.
+    seq_pers_ms = one_by_one("persistent", prms)
     log("batched: one by one (persistent) done")
     same = bool(torch.equal(out, batch_img))
-    seq_lv_ms = one_by_one("levels")
-    log("batched: one by one (levels) done")
+    one_by_one("levels", prms)
+    log("batched: one by one (levels, same parameters) done")
     same = same and bool(torch.equal(out, batch_img))
+    # The per-level form timed with its own parameters (it computes leaves whole).
+    lv_prms = [workloads.batch_params_levels(w.W) for w in ims]
+    seq_lv_ms = one_by_one("levels", lv_prms)
+    log("batched: one by one (levels, its parameters) done")
     del out, batch_img
     return {"workload": "batch-%d-boundary-images" % count, "images": count, "pixels": total,
             "ms": round(ms, 3), "mpix_s": round(total / (ms * 1e-3) / 1e6, 1),
@@ -140,6 +145,7 @@ def batched_leg(ctx, torch, ask, workloads, sp, count, steps):
                                / PEAK_FP64_TFLOPS, 4),
             "one_by_one_persistent_ms": round(seq_pers_ms, 3),
             "one_by_one_levels_ms": round(seq_lv_ms, 3),
+            "one_by_one_levels_params": "g = side/256, r = 2, B = 32",
             "speedup_vs_one_by_one_levels": round(seq_lv_ms / ms, 2),
             "equals_one_by_one": same}
 
@@ -241,8 +247,10 @@ def served_leg(ctx, ask, workloads, seconds):
     res = serve.serve(ctx, sched, params_of, slots=64, log=log)
     res.pop("images")
     log("served: done; sequential per-level renders of the same requests")
-    seq_s = serve.sequential(ctx, [w for _, w in sched], params_of, "levels")
+    seq_s = serve.sequential(ctx, [w for _, w in sched],
+                             lambda w: workloads.batch_params_levels(w.W), "levels")
     res["sequential_levels_mpix_s"] = round(res["pixels"] / seq_s / 1e6, 1)
+    res["sequential_levels_params"] = "g = side/256, r = 2, B = 32"
     res["arrival_seconds"] = seconds
     for k in ("offered_mpix_s", "achieved_mpix_s", "makespan_s", "latency_p50_ms",
               "latency_p99_ms", "latency_max_ms"):

@@ -55,6 +55,12 @@ def test_serving_requests_shape():
 
 
 def test_batch_params():
-    assert W.batch_params(512) == W.Params(2, 2, 32)
-    assert W.batch_params(8191) == W.Params(31, 2, 32)
-    assert W.batch_params(300) == W.Params(1, 2, 32)
+    assert W.batch_params(512) == W.Params(2, 2, 128)
+    assert W.batch_params(8191) == W.Params(31, 2, 128)
+    assert W.batch_params(300) == W.Params(1, 2, 128)
+
+
+def test_batch_params_levels():
+    assert W.batch_params_levels(512) == W.Params(2, 2, 32)
+    assert W.batch_params_levels(8191) == W.Params(31, 2, 32)
+    assert W.batch_params_levels(300).B == 32

@@ -152,8 +152,17 @@ JULIA_PARAMS = Params(64, 4, 16)
 
 def batch_params(side):
     """(g, r, B) for a batch or serving image of the given side: level-0
-    regions of about 256 pixels, r = 2, B = 32 (the best setting of the
-    16384 x 16384 sweep, scaled to the image)."""
+    regions of about 256 pixels, r = 2, B = 128. These images zoom onto the
+    set's boundary, where most work is leaf work; leaves of up to 128 x 128
+    (queued as bands) measured fastest on the 256-image batch: 789 ms
+    against 905 ms for B = 32, 805 ms for B = 64."""
+    return Params(max(1, min(256, side // 256)), 2, 128)
+
+
+def batch_params_levels(side):
+    """(g, r, B) for the same images in the per-level form, which computes
+    every leaf whole on one wave: B = 32 keeps its leaves small (one by one,
+    the 256 batch images take 1.7 s with B = 32 and 3.2 s with B = 128)."""
     return Params(max(1, min(256, side // 256)), 2, 32)
 
 
