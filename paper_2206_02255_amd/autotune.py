@@ -83,8 +83,8 @@ def sweep(ctx, win, grid, form="persistent", reps=3, out=None):
 
 
 def compare_schemes(ctx, win, g, r, B, bands=(ask.BAND_NONE, 4096, 1024, 256), reps=5, q=256,
-                    c=64, lam=1.0):
-    """Persistent render of ``win`` with (g, r, B) for every leaf band size of
+                    c=64, lam=1.0, form="persistent"):
+    """Render of ``win`` in ``form`` with (g, r, B) for every leaf band size of
     ``bands`` (ask.BAND_NONE: SBR, each leaf on the wave that decides it;
     others: MBR, leaves above that many pixels shared out as row bands). Returns
     the measured kernel times (best and median of ``reps``) and the cost
@@ -97,7 +97,7 @@ def compare_schemes(ctx, win, g, r, B, bands=(ask.BAND_NONE, 4096, 1024, 256), r
     P = None
     try:
         for band in bands:
-            prm = ask.params(g, r, B, "persistent", band)
+            prm = ask.params(g, r, B, form, band)
             st = ask.ask_dwell_subdiv(ctx, win, prm, out.data_ptr(), stream, want_stats=True)
             P = costmodel.split_probability(st)
             ms = []
@@ -115,7 +115,7 @@ def compare_schemes(ctx, win, g, r, B, bands=(ask.BAND_NONE, 4096, 1024, 256), r
     t_mbr = float(costmodel.time_mbr(n, g, r, B, A, P, lam, q, c))
     sbr = rows[0]["best_ms"] if bands[0] == ask.BAND_NONE else None
     best_mbr = min((row["best_ms"] for row in rows if row["band"] != "none (SBR)"), default=None)
-    return {"g": g, "r": r, "B": B, "P": P, "lambda": lam, "rows": rows,
+    return {"g": g, "r": r, "B": B, "form": form, "P": P, "lambda": lam, "rows": rows,
             "model": {"T_SBR": t_sbr, "T_MBR": t_mbr, "T_MBR/T_SBR": t_mbr / t_sbr},
             "measured": {"best_MBR/SBR": (best_mbr / sbr) if sbr and best_mbr else None}}
 
@@ -274,7 +274,7 @@ def main(argv=None):
         try:
             props = torch.cuda.get_device_properties(0)
             res = compare_schemes(ctx, ask.window(w), g, r, B, reps=args.reps,
-                                  q=props.multi_processor_count)
+                                  q=props.multi_processor_count, form=args.form)
         finally:
             ask.ask_destroy(ctx)
         for row in res["rows"]:

@@ -489,7 +489,13 @@ ask_status render(ask_ctx *ctx, const Image *ims, uint32_t n, uint32_t form, hip
     uint64_t widest = 0;
     for (uint32_t lv = 0; lv < levels; ++lv)
         widest = std::max(widest, bound[lv]);
-    const uint64_t need = form == ASK_FORM_PERSISTENT ? b.queue_entries() : widest;
+    // Per-level form: a level's table holds its regions and the bands of the
+    // leaves decided one level up, at most pixels / (band / 2) plus one per
+    // leaf; bands of last-level leaves take one more level kernel.
+    const bool banded = b.band != ASK_BAND_NONE;
+    const uint64_t band_bound = banded ? b.pixels / (b.band / 2) + widest : 0;
+    const uint64_t need =
+        form == ASK_FORM_PERSISTENT ? b.queue_entries() : widest + band_bound;
     const uint64_t want = std::min<uint64_t>(need, kQueueBudget);
     const bool may_overflow = need > want;
     if (capturing && (may_overflow || (form == ASK_FORM_PERSISTENT ? ctx->queue_cap < want
@@ -610,7 +616,7 @@ ask_status render(ask_ctx *ctx, const Image *ims, uint32_t n, uint32_t form, hip
         if (e != hipSuccess)
             return hip_fail(ctx, e, "seed kernel launch");
         const uint32_t resident = (uint32_t)(ctx->cus * ctx->occ_level);
-        for (uint32_t lv = 0; lv < levels; ++lv) {
+        for (uint32_t lv = 0; lv < levels + (banded ? 1u : 0u); ++lv) {
             a.level = lv;
             a.in = ctx->lvq[lv & 1];
             a.out = ctx->lvq[(lv + 1) & 1];
@@ -627,8 +633,9 @@ ask_status render(ask_ctx *ctx, const Image *ims, uint32_t n, uint32_t form, hip
                     break;
                 e = launch_level_exact(a, cnt, s);
             } else {
+                const uint64_t entries = bound[lv] + (lv > 0 ? band_bound : 0);
                 const uint64_t blocks =
-                    std::min<uint64_t>(resident, (bound[lv] + kWavesPerBlock - 1) / kWavesPerBlock);
+                    std::min<uint64_t>(resident, (entries + kWavesPerBlock - 1) / kWavesPerBlock);
                 e = launch_level(a, (uint32_t)std::max<uint64_t>(1, blocks), s);
             }
             if (e != hipSuccess)

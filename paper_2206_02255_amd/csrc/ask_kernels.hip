@@ -519,14 +519,20 @@ __device__ void split_region(const SubdivArgs &a, uint32_t img, uint32_t x, uint
     });
 }
 
-// Queue forms: the per-pixel work of a leaf becomes row bands of about
-// `band` pixels, queued as leaf entries that any wave can take.
+// The per-pixel work of a leaf as row bands of about `band` pixels, leaf
+// entries that any wave can take (several blocks per region, MBR, Sec.
+// 4.3.2): in the queue forms appended to the queue, in the per-level form to
+// the next level's table, whose kernel computes them beside that level's
+// regions.
+template <bool kQueue>
 __device__ void queue_leaf_bands(const SubdivArgs &a, uint32_t img, uint32_t x, uint32_t y,
                                  uint32_t w, uint32_t h, uint32_t band, uint32_t level,
                                  uint32_t lane) {
     const uint32_t hb = max(1u, band / w);
     const uint32_t nb = (h + hb - 1) / hb;
-    emit_entries<true>(a, a.queue, &a.ctrl[kTail], a.cap, nb, kLeaf, level, lane,
+    Region *q = kQueue ? a.queue : a.out;
+    uint32_t *tail = kQueue ? &a.ctrl[kTail] : &a.ctrl[kCount + level + 1];
+    emit_entries<kQueue>(a, q, tail, a.cap, nb, kLeaf, level, lane,
                        [&](uint32_t j, Region &e) {
                            const uint32_t y0 = y + j * hb;
                            e.img = img;
@@ -556,8 +562,8 @@ __device__ void decide_region(const SubdivArgs &a, uint32_t img, const Image &im
     if (w <= im.B && h <= im.B) {
         if (st)
             wave_add64(&st->leaves[level], 1ull);
-        if (kQueue && w * h > im.band) {
-            queue_leaf_bands(a, img, x, y, w, h, im.band, level, lane);
+        if (w * h > im.band) {
+            queue_leaf_bands<kQueue>(a, img, x, y, w, h, im.band, level, lane);
             return;
         }
         unsigned long long li = leaf_region(im, x, y, w, h);

@@ -297,10 +297,12 @@ def test_persistent_wait_limit_reports_timeout(gpu, ref):
     ask.ask_synchronize(ctx, stream)
 
 
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("band", [0xffffffff, 64, 200, 4096])
-def test_persistent_leaf_bands(gpu, ref, band):
-    """Leaf work shared by several waves (row bands of `band` pixels) or kept
-    on the deciding wave (0xffffffff): the same image and counters."""
+def test_leaf_bands(gpu, ref, form, band):
+    """Leaf work shared by several waves (row bands of `band` pixels, queued
+    or put in the next level's table) or kept on the deciding wave
+    (0xffffffff): the same image and counters in every form."""
     ask, ctx, torch = gpu
     cases = [(Window(-1.5, 0.5, -1.0, 1.0, 600, 517, 700), 4, 2, 128),
              (Window(-0.75, -0.73, 0.1, 0.12, 400, 300, 3000), 2, 3, 200),
@@ -308,7 +310,7 @@ def test_persistent_leaf_bands(gpu, ref, band):
     for w, g, r, B in cases:
         print(band, w, (g, r, B), flush=True)
         out = _out(torch, w)
-        st = ask.ask_dwell_subdiv(ctx, ask.window(w), ask.params(g, r, B, "persistent", band),
+        st = ask.ask_dwell_subdiv(ctx, ask.window(w), ask.params(g, r, B, form, band),
                                   out.data_ptr(), torch.cuda.current_stream().cuda_stream,
                                   want_stats=True)
         want, rst = ref.subdiv(w, g, r, B)
