@@ -160,9 +160,9 @@ def batch_params(side):
 
 
 def batch_params_levels(side):
-    """(g, r, B) for the same images in the per-level form, which computes
-    every leaf whole on one wave: B = 32 keeps its leaves small (one by one,
-    the 256 batch images take 1.7 s with B = 32 and 3.2 s with B = 128)."""
+    """(g, r, B) with smaller leaves, B = 32, the per-level form's setting of
+    the 16384 x 16384 sweep: the benchmark's per-level baselines for batch
+    and serving images take the faster of this and batch_params."""
     return Params(max(1, min(256, side // 256)), 2, 32)
 
 
