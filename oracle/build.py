@@ -1,13 +1,15 @@
 """Build the CPU oracle library (test infrastructure).
 
-Compiles ``askref.c`` with gcc at -O2, with floating-point contraction off and
-no fast-math, so that every binary64 operation is rounded on its own.
+Compiles ``askref.c`` (2-D images) and ``askref3.c`` (3-D volumes) with gcc at
+-O2, with floating-point contraction off and no fast-math, so that every
+binary64 operation is rounded on its own.
 """
 import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libaskref.so")
+LIB3 = os.path.join(HERE, "libaskref3.so")
 FLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fPIC",
          "-shared", "-pthread", "-Wall", "-Wextra", "-Werror"]
 
@@ -24,5 +26,11 @@ def build(extra=(), src=None, out=None):
     return out
 
 
+def build3():
+    """Compile the 3-D oracle (``askref3.c``) and return the library path."""
+    return build(src=os.path.join(HERE, "askref3.c"), out=LIB3)
+
+
 if __name__ == "__main__":
     print(build())
+    print(build3())

@@ -150,6 +150,36 @@ JULIA = Window(-1.7, 1.7, -1.7, 1.7, 16384, 16384, 2048, julia=JULIA_C)
 JULIA_PARAMS = Params(64, 4, 16)
 
 
+@dataclass(frozen=True)
+class Volume:
+    """Box of points [x0, x1] x [y0, y1] x [z0, z1] sampled at W x H x L voxel
+    centres, maximum dwell D, for the quaternion Julia set of c = (cr, ci):
+    a voxel's point is q0 = x + y i + z j. The j = 0 slice is the filled
+    Julia set of the complex c. Volumes are stored x fastest, then y, then z."""
+    x0: float
+    x1: float
+    y0: float
+    y1: float
+    z0: float
+    z1: float
+    W: int
+    H: int
+    L: int
+    D: int
+    c: tuple = (-1.0, 0.0)
+
+    @property
+    def voxels(self):
+        return self.W * self.H * self.L
+
+
+# The 3-D workload: 512^3 voxels over [-1.6, 1.6]^3, dwell limit 256, for a c
+# off the real axis (no rotational symmetry), level-0 grid 16^3, r = 2, B = 8.
+VOLUME_C = (-0.2, 0.8)
+VOLUME = Volume(-1.6, 1.6, -1.6, 1.6, -1.6, 1.6, 512, 512, 512, 256, c=VOLUME_C)
+VOLUME_PARAMS = Params(16, 2, 8)
+
+
 def batch_params(side):
     """(g, r, B) for a batch or serving image of the given side: level-0
     regions of about 256 pixels, r = 2, B = 128. These images zoom onto the
