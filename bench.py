@@ -79,6 +79,7 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--no-deep", action="store_true", help="skip the deep-zoom image")
     ap.add_argument("--no-julia", action="store_true", help="skip the Julia-set image")
+    ap.add_argument("--no-volume", action="store_true", help="skip the 3-D volume")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first copy BYTES of device memory once (a plain copy kernel of known "
                          "size, to scale the memory-traffic counters of a profile)")
@@ -240,6 +241,64 @@ def julia_leg(ctx, torch, ask, workloads, sp, steps):
     return res
 
 
+# binary64 operations of one quaternion Julia iteration: 5 products (three
+# squares, two cross terms), 7 sums for the new parts, 2 sums for the squared
+# modulus (its squares are the next iteration's).
+FLOPS_PER_QUAT_ITERATION = 14
+
+
+def volume_leg(torch, ask, workloads, sp, steps):
+    """The 3-D extension: the quaternion Julia volume of c = -0.2 + 0.6i at
+    512^3 voxels, D = 256, exhaustive and level-by-level subdivision with
+    both curves."""
+    v, p = workloads.VOLUME, workloads.VOLUME_PARAMS
+    vol = ask.volume(v)
+    out = torch.empty(v.voxels, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, n):
+        ms = []
+        for _ in range(n):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            b.synchronize()
+            ms.append(a.elapsed_time(b))
+        ms.sort()
+        return ms[len(ms) // 2]
+
+    log("volume: %s, exhaustive" % (v,))
+    ex_fn = lambda: ask.ask3_dwell_exhaustive(vol, out.data_ptr(), sp)  # noqa: E731
+    ex_fn()
+    ex_ms = timed(ex_fn, 3)
+    ex_iters = int(out.to(torch.int64).sum().item())
+    ex = out.clone()
+    res = {"workload": "quaternion-julia-512^3-D256", "c": list(v.c),
+           "box": [v.x0, v.x1, v.y0, v.y1, v.z0, v.z1], "g": p.g, "r": p.r, "B": p.B,
+           "exhaustive": {"ms": round(ex_ms, 3), "dwell_iterations": ex_iters,
+                          "mvox_s": round(v.voxels / (ex_ms * 1e-3) / 1e6, 1),
+                          "fp64_frac": round(FLOPS_PER_QUAT_ITERATION * ex_iters / (ex_ms * 1e-3)
+                                             / 1e12 / PEAK_FP64_TFLOPS, 4)}}
+    for curve in ("canonical", "morton"):
+        log("volume: subdivision, %s curve" % curve)
+        prm = ask.params3(p.g, p.r, p.B, curve)
+        nbytes = ask.ask3_workspace_bytes(vol, prm)
+        work = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        st = ask.ask3_dwell_subdiv(vol, prm, out.data_ptr(), work.data_ptr(), nbytes, sp,
+                                   want_stats=True)
+        fn = lambda: ask.ask3_dwell_subdiv(vol, prm, out.data_ptr(), work.data_ptr(),  # noqa: E731
+                                           nbytes, sp)
+        ms = timed(fn, max(3, steps))
+        res[curve] = {"ms": round(ms, 3), "mvox_s": round(v.voxels / (ms * 1e-3) / 1e6, 1),
+                      "speedup_vs_exhaustive": round(ex_ms / ms, 2),
+                      "levels": st["levels"], "regions": st["regions"],
+                      "voxels_differing_from_exhaustive": int((out != ex).sum().item())}
+        del work
+    del out, ex
+    return res
+
+
 def served_leg(ctx, ask, workloads, seconds):
     """Poisson arrivals at 200/s into the server kernel, and the same requests
     rendered back to back by the per-level form."""
@@ -396,6 +455,8 @@ def main():
         result["forms"]["deep"] = deep_leg(ctx, torch, ask, workloads, sp)
     if not args.no_julia:
         result["forms"]["julia"] = julia_leg(ctx, torch, ask, workloads, sp, args.steps)
+    if not args.no_volume:
+        result["forms"]["volume"] = volume_leg(torch, ask, workloads, sp, args.steps)
 
     if not args.no_cpu_baseline:
         import numpy as np

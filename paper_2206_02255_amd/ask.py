@@ -59,7 +59,35 @@ class ask_stats(C.Structure):
         return d
 
 
-# Every symbol include/ask.h declares, with its C signature.
+CURVE_CANONICAL, CURVE_MORTON = 0, 1
+CURVES = {"canonical": CURVE_CANONICAL, "morton": CURVE_MORTON}
+MAX_LEVELS3 = 32
+
+
+class ask_volume(C.Structure):
+    _fields_ = [("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
+                ("z0", C.c_double), ("z1", C.c_double), ("W", C.c_uint32), ("H", C.c_uint32),
+                ("L", C.c_uint32), ("D", C.c_uint32), ("cr", C.c_double), ("ci", C.c_double)]
+
+
+class ask3_params(C.Structure):
+    _fields_ = [("g", C.c_uint32), ("r", C.c_uint32), ("B", C.c_uint32), ("curve", C.c_uint32)]
+
+
+class ask3_stats(C.Structure):
+    _fields_ = [("levels", C.c_uint32), ("overflow", C.c_uint32),
+                ("regions", C.c_uint64 * MAX_LEVELS3), ("fills", C.c_uint64 * MAX_LEVELS3),
+                ("splits", C.c_uint64 * MAX_LEVELS3), ("leaves", C.c_uint64 * MAX_LEVELS3)]
+
+    def as_dict(self):
+        n = self.levels
+        d = {"levels": n, "overflow": self.overflow}
+        for k in ("regions", "fills", "splits", "leaves"):
+            d[k] = list(getattr(self, k)[:n])
+        return d
+
+
+# Every symbol include/ask.h and include/ask3d.h declare, with its C signature.
 _P = C.c_void_p
 SIGNATURES = {
     "ask_status_str": (C.c_char_p, [C.c_int]),
@@ -87,6 +115,12 @@ SIGNATURES = {
     "ask_server_poll": (C.c_int, [_P, C.c_uint64, C.POINTER(C.c_int)]),
     "ask_server_in_flight": (C.c_int, [_P, C.POINTER(C.c_uint32)]),
     "ask_server_destroy": (C.c_int, [_P]),
+    "ask3_validate": (C.c_int, [C.POINTER(ask_volume), C.POINTER(ask3_params)]),
+    "ask3_workspace_bytes": (C.c_int, [C.POINTER(ask_volume), C.POINTER(ask3_params),
+                                       C.POINTER(C.c_uint64)]),
+    "ask3_dwell_exhaustive": (C.c_int, [C.POINTER(ask_volume), _P, _P]),
+    "ask3_dwell_subdiv": (C.c_int, [C.POINTER(ask_volume), C.POINTER(ask3_params), _P, _P,
+                                    C.c_uint64, _P, C.POINTER(ask3_stats)]),
 }
 
 
@@ -266,6 +300,39 @@ def ask_server_in_flight(sv):
 def ask_server_destroy(sv):
     ctx = _live_servers.pop(sv.value, None)
     _check(lib.ask_server_destroy(sv), ctx)
+
+
+def volume(v):
+    """ask_volume of a volume description (x0..z1, W, H, L, D, c = (cr, ci))."""
+    return ask_volume(float(v.x0), float(v.x1), float(v.y0), float(v.y1), float(v.z0),
+                      float(v.z1), int(v.W), int(v.H), int(v.L), int(v.D), float(v.c[0]),
+                      float(v.c[1]))
+
+
+def params3(g, r, B, curve="canonical"):
+    return ask3_params(int(g), int(r), int(B), CURVES[curve] if isinstance(curve, str) else curve)
+
+
+def ask3_validate(vol, prm=None):
+    return lib.ask3_validate(C.byref(vol), C.byref(prm) if prm is not None else None)
+
+
+def ask3_workspace_bytes(vol, prm):
+    n = C.c_uint64()
+    _check(lib.ask3_workspace_bytes(C.byref(vol), C.byref(prm), C.byref(n)))
+    return n.value
+
+
+def ask3_dwell_exhaustive(vol, d_out, stream=0):
+    _check(lib.ask3_dwell_exhaustive(C.byref(vol), _P(d_out), _P(stream)))
+
+
+def ask3_dwell_subdiv(vol, prm, d_out, d_work, work_bytes, stream=0, want_stats=False):
+    st = ask3_stats() if want_stats else None
+    _check(lib.ask3_dwell_subdiv(C.byref(vol), C.byref(prm), _P(d_out), _P(d_work),
+                                 int(work_bytes), _P(stream),
+                                 C.byref(st) if st is not None else None))
+    return st.as_dict() if st is not None else None
 
 
 def _stop_servers():

@@ -5,7 +5,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libask.so")
-SOURCES = ["csrc/ask_kernels.hip", "csrc/ask_api.hip"]
+SOURCES = ["csrc/ask_kernels.hip", "csrc/ask_api.hip", "csrc/ask3d.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # binary64 operations stay separate: no fused multiply-add anywhere

@@ -1,0 +1,498 @@
+// ask3d.hip -- the 3-D extension of the subdivision (the paper's section on
+// subdivisions at higher dimensions): exhaustive and level-by-level
+// subdivision volumes of the quaternion Julia set, the level tables holding
+// one space-filling-curve scalar per box (canonical or Morton order).
+//
+// One wave per box, waves walking their level's table with a grid stride, so
+// a level launch needs no count from the host: the host knows in advance the
+// last level any box can reach (the first whose cells all have sides <= B)
+// and launches that many level kernels back to back, with no read-back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include "ask3d.h"
+
+namespace {
+
+constexpr uint32_t kLanes = 64;
+constexpr uint32_t kThreads = 256;  // 4 waves per workgroup
+constexpr uint32_t kWavesPer = kThreads / kLanes;
+
+// Control block, in 64-bit words: entries per level table (one more word
+// than levels: the last level's children slot), then per-level fills,
+// splits and leaves, then the overflow flag.
+constexpr uint32_t kCountW = 0;
+constexpr uint32_t kFillW = 40;
+constexpr uint32_t kSplitW = kFillW + ASK3_MAX_LEVELS;
+constexpr uint32_t kLeafW = kSplitW + ASK3_MAX_LEVELS;
+constexpr uint32_t kOverW = kLeafW + ASK3_MAX_LEVELS;
+constexpr uint32_t kCtrlWords = kOverW + 8;
+constexpr uint64_t kTableOffset = 4096;
+constexpr uint32_t kMaxCoordBits = 21;  // per axis, so that a Morton scalar fits 63 bits
+
+struct Vol3 {
+    double cx, cy, cz, hx, hy, hz, cr, ci;
+    uint32_t n[3];
+    uint32_t D;
+    uint32_t *out;
+};
+
+struct Level3 {
+    const uint64_t *in;
+    uint64_t *next;
+    unsigned long long *ctrl;
+    uint64_t G, cap;
+    uint32_t r, B, curve, level;
+};
+
+__device__ __forceinline__ double axis_point(double centre, double half, uint32_t p, uint32_t n) {
+    const int64_t k = 2 * (int64_t)p + 1 - (int64_t)n;
+    const double t = (double)k * half;
+    return centre + t;
+}
+
+// q <- q^2 + c with q = a + b i + e j, c = cr + ci i: the first k with
+// |q_k|^2 > 4, else D. b^2 + e^2 is summed first, so e = 0 performs the
+// complex iteration's operations exactly.
+__device__ __forceinline__ uint32_t quat_dwell(double a, double b, double e, double cr,
+                                               double ci, uint32_t D) {
+    for (uint32_t k = 1; k <= D; ++k) {
+        const double a2 = a * a, b2 = b * b, e2 = e * e;
+        const double ab = a * b, ae = a * e;
+        a = (a2 - (b2 + e2)) + cr;
+        b = (ab + ab) + ci;
+        e = (ae + ae) + 0.0;
+        const double mag = a * a + (b * b + e * e);
+        if (mag > 4.0)
+            return k;
+    }
+    return D;
+}
+
+__device__ __forceinline__ uint32_t voxel_dwell(const Vol3 &v, uint32_t x, uint32_t y,
+                                                uint32_t z) {
+    return quat_dwell(axis_point(v.cx, v.hx, x, v.n[0]), axis_point(v.cy, v.hy, y, v.n[1]),
+                      axis_point(v.cz, v.hz, z, v.n[2]), v.cr, v.ci, v.D);
+}
+
+__device__ __forceinline__ void put_voxel(const Vol3 &v, uint32_t x, uint32_t y, uint32_t z,
+                                          uint32_t d) {
+    v.out[((uint64_t)z * v.n[1] + y) * v.n[0] + x] = d;
+}
+
+// ---------------------------------------------------------------------------
+// Space-filling curves over a level's G x G x G cells.
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ uint64_t spread3(uint32_t c) {
+    uint64_t x = c & 0x1fffffu;
+    x = (x | x << 32) & 0x1f00000000ffffull;
+    x = (x | x << 16) & 0x1f0000ff0000ffull;
+    x = (x | x << 8) & 0x100f00f00f00f00full;
+    x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+    x = (x | x << 2) & 0x1249249249249249ull;
+    return x;
+}
+
+__host__ __device__ __forceinline__ uint32_t gather3(uint64_t x) {
+    x &= 0x1249249249249249ull;
+    x = (x ^ (x >> 2)) & 0x10c30c30c30c30c3ull;
+    x = (x ^ (x >> 4)) & 0x100f00f00f00f00full;
+    x = (x ^ (x >> 8)) & 0x1f0000ff0000ffull;
+    x = (x ^ (x >> 16)) & 0x1f00000000ffffull;
+    x = (x ^ (x >> 32)) & 0x1fffffull;
+    return (uint32_t)x;
+}
+
+__device__ __forceinline__ uint64_t cell_scalar(const uint32_t p[3], uint64_t G, uint32_t curve) {
+    if (curve == ASK_CURVE_MORTON)
+        return spread3(p[0]) | spread3(p[1]) << 1 | spread3(p[2]) << 2;
+    return ((uint64_t)p[2] * G + p[1]) * G + p[0];
+}
+
+__device__ __forceinline__ void scalar_cell(uint64_t s, uint64_t G, uint32_t curve, uint32_t p[3]) {
+    if (curve == ASK_CURVE_MORTON) {
+        p[0] = gather3(s);
+        p[1] = gather3(s >> 1);
+        p[2] = gather3(s >> 2);
+        return;
+    }
+    p[0] = (uint32_t)(s % G);
+    s /= G;
+    p[1] = (uint32_t)(s % G);
+    p[2] = (uint32_t)(s / G);
+}
+
+__device__ __forceinline__ uint32_t cell_lo(uint64_t j, uint64_t G, uint32_t n) {
+    return (uint32_t)(j * (uint64_t)n / G);
+}
+
+// Cell p of a G-grid as a box; false when it is empty or outside the grid.
+__device__ __forceinline__ bool cell_box(const Vol3 &v, uint64_t G, const uint32_t p[3],
+                                         uint32_t lo[3], uint32_t hi[3]) {
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        ok = ok && (uint64_t)p[d] < G;
+        lo[d] = cell_lo(p[d], G, v.n[d]);
+        hi[d] = cell_lo((uint64_t)p[d] + 1, G, v.n[d]);
+        ok = ok && lo[d] < hi[d] && hi[d] <= v.n[d];
+    }
+    return ok;
+}
+
+__device__ __forceinline__ uint64_t wave_base(unsigned long long *counter, uint64_t mask,
+                                              uint32_t lane) {
+    uint64_t base = 0;
+    if (lane == 0 && mask)
+        base = atomicAdd(counter, (unsigned long long)__popcll(mask));
+    const uint32_t lo = __shfl((uint32_t)base, 0), hi = __shfl((uint32_t)(base >> 32), 0);
+    return (uint64_t)hi << 32 | lo;
+}
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask, uint32_t lane) {
+    return (uint32_t)__popcll(mask & ((1ull << lane) - 1));
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+
+// Every voxel: a workgroup owns a 16 x 16 tile of one z slice.
+__global__ __launch_bounds__(kThreads) void exhaustive3_kernel(Vol3 v, uint32_t tiles_x,
+                                                               uint32_t tiles_y) {
+    uint32_t b = blockIdx.x;
+    const uint32_t bx = b % tiles_x;
+    b /= tiles_x;
+    const uint32_t by = b % tiles_y;
+    const uint32_t z = b / tiles_y;
+    const uint32_t x = bx * 16 + (threadIdx.x & 15);
+    const uint32_t y = by * 16 + (threadIdx.x >> 4);
+    if (x < v.n[0] && y < v.n[1] && z < v.n[2])
+        put_voxel(v, x, y, z, voxel_dwell(v, x, y, z));
+}
+
+__global__ __launch_bounds__(kThreads) void reset3_kernel(unsigned long long *ctrl) {
+    for (uint32_t i = threadIdx.x; i < kCtrlWords; i += kThreads)
+        ctrl[i] = 0;
+}
+
+// Level 0: the non-empty cells of the g x g x g grid.
+__global__ __launch_bounds__(kThreads) void seed3_kernel(Vol3 v, uint64_t *table,
+                                                         unsigned long long *ctrl, uint32_t g,
+                                                         uint32_t curve, uint64_t cap) {
+    const uint32_t lane = threadIdx.x & (kLanes - 1);
+    const uint64_t cells = (uint64_t)g * g * g;
+    const uint64_t stride = (uint64_t)gridDim.x * kThreads;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * kThreads + (threadIdx.x & ~(kLanes - 1));
+         i0 < cells; i0 += stride) {
+        const uint64_t i = i0 + lane;
+        uint32_t p[3] = {0, 0, 0}, lo[3], hi[3];
+        bool ok = false;
+        if (i < cells) {
+            p[0] = (uint32_t)(i % g);
+            p[1] = (uint32_t)((i / g) % g);
+            p[2] = (uint32_t)(i / ((uint64_t)g * g));
+            ok = cell_box(v, g, p, lo, hi);
+        }
+        const uint64_t mask = __ballot(ok);
+        const uint64_t base = wave_base(&ctrl[kCountW], mask, lane);
+        if (ok) {
+            const uint64_t at = base + lanes_below(mask, lane);
+            if (at < cap)
+                table[at] = cell_scalar(p, g, curve);
+            else
+                atomicOr(&ctrl[kOverW], 1ull);
+        }
+    }
+}
+
+// Voxel t of the surface of a w x h x l box: the two z faces, then the
+// rectangular ring of each inner slice. A box with a side of 1 or 2 is all
+// surface and is walked in storage order.
+__device__ __forceinline__ uint32_t surface_count(uint32_t w, uint32_t h, uint32_t l) {
+    if (w <= 2 || h <= 2 || l <= 2)
+        return w * h * l;
+    return 2 * w * h + (l - 2) * (2 * w + 2 * (h - 2));
+}
+
+__device__ __forceinline__ void surface_voxel(uint32_t t, uint32_t w, uint32_t h, uint32_t l,
+                                              uint32_t &x, uint32_t &y, uint32_t &z) {
+    if (w <= 2 || h <= 2 || l <= 2) {
+        x = t % w;
+        y = (t / w) % h;
+        z = t / (w * h);
+        return;
+    }
+    const uint32_t face = w * h;
+    if (t < 2 * face) {
+        z = t < face ? 0 : l - 1;
+        t = t < face ? t : t - face;
+        x = t % w;
+        y = t / w;
+        return;
+    }
+    const uint32_t ring = 2 * w + 2 * (h - 2);
+    const uint32_t u = t - 2 * face;
+    z = 1 + u / ring;
+    const uint32_t q = u % ring;
+    if (q < w) {
+        x = q, y = 0;
+    } else if (q < 2 * w) {
+        x = q - w, y = h - 1;
+    } else {
+        const uint32_t q2 = q - 2 * w;
+        x = (q2 & 1) ? w - 1 : 0;
+        y = 1 + q2 / 2;
+    }
+}
+
+// One level: each wave takes boxes from the level's table and decides them
+// (surface uniform -> fill; every side <= B -> every voxel; else split).
+__global__ __launch_bounds__(kThreads) void level3_kernel(Vol3 v, Level3 L) {
+    const uint32_t lane = threadIdx.x & (kLanes - 1);
+    const uint64_t wave = (uint64_t)blockIdx.x * kWavesPer + threadIdx.x / kLanes;
+    const uint64_t waves = (uint64_t)gridDim.x * kWavesPer;
+    const uint64_t count = std::min((uint64_t)L.ctrl[kCountW + L.level], L.cap);
+    unsigned long long nfill = 0, nsplit = 0, nleaf = 0;
+    for (uint64_t e = wave; e < count; e += waves) {
+        uint32_t p[3], lo[3], hi[3];
+        scalar_cell(L.in[e], L.G, L.curve, p);
+        if (!cell_box(v, L.G, p, lo, hi)) {
+            if (lane == 0)
+                atomicOr(&L.ctrl[kOverW], 2ull);
+            continue;
+        }
+        const uint32_t w = hi[0] - lo[0], h = hi[1] - lo[1], l = hi[2] - lo[2];
+        const uint32_t first = voxel_dwell(v, lo[0], lo[1], lo[2]);
+        const uint32_t S = surface_count(w, h, l);
+        bool uniform = true;
+        for (uint32_t t0 = 0; t0 < S; t0 += kLanes) {
+            const uint32_t t = t0 + lane;
+            bool differs = false;
+            if (t < S) {
+                uint32_t x, y, z;
+                surface_voxel(t, w, h, l, x, y, z);
+                differs = voxel_dwell(v, lo[0] + x, lo[1] + y, lo[2] + z) != first;
+            }
+            if (__ballot(differs)) {
+                uniform = false;
+                break;
+            }
+        }
+        const uint32_t wh = w * h, n = wh * l;
+        if (uniform) {
+            for (uint32_t t = lane; t < n; t += kLanes)
+                put_voxel(v, lo[0] + t % w, lo[1] + (t / w) % h, lo[2] + t / wh, first);
+            ++nfill;
+        } else if (w <= L.B && h <= L.B && l <= L.B) {
+            for (uint32_t t = lane; t < n; t += kLanes) {
+                const uint32_t x = lo[0] + t % w, y = lo[1] + (t / w) % h, z = lo[2] + t / wh;
+                put_voxel(v, x, y, z, voxel_dwell(v, x, y, z));
+            }
+            ++nleaf;
+        } else {
+            const uint32_t r = L.r, kids = r * r * r;
+            const uint64_t G1 = L.G * r;
+            for (uint32_t k0 = 0; k0 < kids; k0 += kLanes) {
+                const uint32_t k = k0 + lane;
+                uint32_t c[3] = {0, 0, 0}, clo[3], chi[3];
+                bool ok = false;
+                if (k < kids) {
+                    c[0] = p[0] * r + k % r;
+                    c[1] = p[1] * r + (k / r) % r;
+                    c[2] = p[2] * r + k / (r * r);
+                    ok = cell_box(v, G1, c, clo, chi);
+                }
+                const uint64_t mask = __ballot(ok);
+                const uint64_t base = wave_base(&L.ctrl[kCountW + L.level + 1], mask, lane);
+                if (ok) {
+                    const uint64_t at = base + lanes_below(mask, lane);
+                    if (at < L.cap)
+                        L.next[at] = cell_scalar(c, G1, L.curve);
+                    else
+                        atomicOr(&L.ctrl[kOverW], 1ull);
+                }
+            }
+            ++nsplit;
+        }
+    }
+    if (lane == 0) {
+        if (nfill)
+            atomicAdd(&L.ctrl[kFillW + L.level], nfill);
+        if (nsplit)
+            atomicAdd(&L.ctrl[kSplitW + L.level], nsplit);
+        if (nleaf)
+            atomicAdd(&L.ctrl[kLeafW + L.level], nleaf);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+bool volume_ok(const ask_volume *v) {
+    if (!v)
+        return false;
+    const double c[8] = {v->x0, v->x1, v->y0, v->y1, v->z0, v->z1, v->cr, v->ci};
+    for (double d : c)
+        if (!std::isfinite(d))
+            return false;
+    if (!(v->x0 < v->x1 && v->y0 < v->y1 && v->z0 < v->z1))
+        return false;
+    const uint32_t n[3] = {v->W, v->H, v->L};
+    for (uint32_t d : n)
+        if (d < 1 || d > 65536)
+            return false;
+    // at most 2^31 voxels: the per-lane 32-bit voxel counters then never wrap
+    return v->D >= 1 && (uint64_t)v->W * v->H * v->L <= (1ull << 31);
+}
+
+// Levels any box can reach: the first level whose cells all have sides <= B
+// is the last; 0 when that takes more than ASK3_MAX_LEVELS levels or a grid
+// wider than 2^21 cells.
+uint32_t reachable_levels(const ask_volume *v, const ask3_params *p) {
+    const uint32_t n = std::max(v->W, std::max(v->H, v->L));
+    uint64_t G = p->g;
+    for (uint32_t i = 0; i < ASK3_MAX_LEVELS; ++i) {
+        if (G > (1ull << kMaxCoordBits))
+            return 0;
+        if ((n + G - 1) / G <= p->B)
+            return i + 1;
+        G *= p->r;
+    }
+    return 0;
+}
+
+bool params_ok(const ask_volume *v, const ask3_params *p) {
+    if (!p || p->g < 1 || p->g > 1024 || p->r < 2 || p->r > 16 || p->B < 1 ||
+        (p->curve != ASK_CURVE_CANONICAL && p->curve != ASK_CURVE_MORTON))
+        return false;
+    return reachable_levels(v, p) != 0;
+}
+
+uint64_t table_cap(const ask_volume *v, const ask3_params *p) {
+    const uint64_t V = (uint64_t)v->W * v->H * v->L;
+    const uint64_t level0 = (uint64_t)std::min(p->g, v->W) * std::min(p->g, v->H) *
+                            std::min(p->g, v->L);
+    const uint64_t r3 = (uint64_t)p->r * p->r * p->r;
+    const uint64_t cap = std::min(V, std::max(level0, r3 * (V / ((uint64_t)p->B + 1))));
+    return (cap + 31) / 32 * 32;
+}
+
+Vol3 make_vol(const ask_volume *v, uint32_t *out) {
+    Vol3 o;
+    o.cx = 0.5 * (v->x0 + v->x1);
+    o.cy = 0.5 * (v->y0 + v->y1);
+    o.cz = 0.5 * (v->z0 + v->z1);
+    o.hx = (v->x1 - v->x0) / (2.0 * (double)v->W);
+    o.hy = (v->y1 - v->y0) / (2.0 * (double)v->H);
+    o.hz = (v->z1 - v->z0) / (2.0 * (double)v->L);
+    o.cr = v->cr;
+    o.ci = v->ci;
+    o.n[0] = v->W, o.n[1] = v->H, o.n[2] = v->L;
+    o.D = v->D;
+    o.out = out;
+    return o;
+}
+
+ask_status launched() {
+    return hipGetLastError() == hipSuccess ? ASK_OK : ASK_EDEVICE;
+}
+
+}  // namespace
+
+extern "C" ask_status ask3_validate(const ask_volume *v, const ask3_params *p) {
+    if (!volume_ok(v))
+        return ASK_EINVAL;
+    if (p && !params_ok(v, p))
+        return ASK_EINVAL;
+    return ASK_OK;
+}
+
+extern "C" ask_status ask3_workspace_bytes(const ask_volume *v, const ask3_params *p,
+                                           uint64_t *bytes) {
+    if (!bytes || !volume_ok(v) || !params_ok(v, p))
+        return ASK_EINVAL;
+    *bytes = kTableOffset + 2 * table_cap(v, p) * sizeof(uint64_t);
+    return ASK_OK;
+}
+
+extern "C" ask_status ask3_dwell_exhaustive(const ask_volume *v, uint32_t *d_out, void *stream) {
+    if (!volume_ok(v) || !d_out)
+        return ASK_EINVAL;
+    const uint32_t tx = (v->W + 15) / 16, ty = (v->H + 15) / 16;
+    const uint64_t blocks = (uint64_t)tx * ty * v->L;
+    if (blocks >= (1ull << 31))
+        return ASK_EINVAL;
+    hipLaunchKernelGGL(exhaustive3_kernel, dim3((uint32_t)blocks), dim3(kThreads), 0,
+                       (hipStream_t)stream, make_vol(v, d_out), tx, ty);
+    return launched();
+}
+
+extern "C" ask_status ask3_dwell_subdiv(const ask_volume *v, const ask3_params *p,
+                                        uint32_t *d_out, void *d_work, uint64_t work_bytes,
+                                        void *stream, ask3_stats *stats) {
+    uint64_t need = 0;
+    if (!d_out || !d_work || ((uintptr_t)d_work & 255) ||
+        ask3_workspace_bytes(v, p, &need) != ASK_OK || work_bytes < need)
+        return ASK_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+        return ASK_EDEVICE;
+    const uint64_t cap = table_cap(v, p);
+    const uint32_t levels = reachable_levels(v, p);
+    unsigned long long *ctrl = (unsigned long long *)d_work;
+    uint64_t *table[2] = {(uint64_t *)((char *)d_work + kTableOffset),
+                          (uint64_t *)((char *)d_work + kTableOffset) + cap};
+    const Vol3 vol = make_vol(v, d_out);
+    hipLaunchKernelGGL(reset3_kernel, dim3(1), dim3(kThreads), 0, s, ctrl);
+    const uint64_t cells = (uint64_t)p->g * p->g * p->g;
+    const uint32_t seed_blocks = (uint32_t)std::min<uint64_t>((cells + kThreads - 1) / kThreads,
+                                                              (uint64_t)cus * 16);
+    hipLaunchKernelGGL(seed3_kernel, dim3(seed_blocks), dim3(kThreads), 0, s, vol, table[0], ctrl,
+                       p->g, p->curve, cap);
+    const uint64_t level0 = (uint64_t)std::min(p->g, v->W) * std::min(p->g, v->H) *
+                            std::min(p->g, v->L);
+    uint64_t G = p->g;
+    for (uint32_t i = 0; i < levels; ++i, G *= p->r) {
+        Level3 L;
+        L.in = table[i & 1];
+        L.next = table[(i + 1) & 1];
+        L.ctrl = ctrl;
+        L.G = G;
+        L.cap = cap;
+        L.r = p->r;
+        L.B = p->B;
+        L.curve = p->curve;
+        L.level = i;
+        const uint64_t bound = i == 0 ? level0 : cap;
+        const uint32_t blocks = (uint32_t)std::max<uint64_t>(
+            1, std::min<uint64_t>((bound + kWavesPer - 1) / kWavesPer, (uint64_t)cus * 8));
+        hipLaunchKernelGGL(level3_kernel, dim3(blocks), dim3(kThreads), 0, s, vol, L);
+    }
+    ask_status st = launched();
+    if (st != ASK_OK || !stats)
+        return st;
+    unsigned long long host[kCtrlWords];
+    if (hipMemcpyAsync(host, ctrl, sizeof host, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return ASK_EDEVICE;
+    *stats = ask3_stats{};
+    for (uint32_t i = 0; i < levels; ++i) {
+        const uint64_t n = std::min<uint64_t>(host[kCountW + i], cap);
+        if (n == 0)
+            break;
+        stats->levels = i + 1;
+        stats->regions[i] = n;
+        stats->fills[i] = host[kFillW + i];
+        stats->splits[i] = host[kSplitW + i];
+        stats->leaves[i] = host[kLeafW + i];
+    }
+    stats->overflow = (uint32_t)host[kOverW];
+    return stats->overflow ? ASK_EOVERFLOW : ASK_OK;
+}

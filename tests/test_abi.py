@@ -1,4 +1,4 @@
-"""The C-ABI library loads, exports every symbol include/ask.h declares, and its
+"""The C-ABI library loads, exports every symbol include/*.h declare, and its
 host-only logic (argument checks, mapping constants, level count) is right.
 No kernel is launched here."""
 import ctypes as C
@@ -20,14 +20,17 @@ def ask():
 
 
 def declared_functions():
-    text = open(os.path.join(ROOT, "include", "ask.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(ask_[a-z_]+)\s*\(", text)))
+    names = set()
+    for h in ("ask.h", "ask3d.h"):
+        text = open(os.path.join(ROOT, "include", h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(ask3?_[a-z_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_every_declared_symbol_is_exported(ask):
     names = declared_functions()
-    assert len(names) >= 9
+    assert len(names) >= 9 and "ask3_dwell_subdiv" in names
     for n in names:
         assert hasattr(ask.lib, n), n
         assert n in ask.SIGNATURES, n
@@ -97,8 +100,12 @@ def test_struct_layouts_match_the_header(tmp_path):
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     fields = {"ask_window": [f for f, _ in ask.ask_window._fields_],
               "ask_params": [f for f, _ in ask.ask_params._fields_],
-              "ask_server_cfg": [f for f, _ in ask.ask_server_cfg._fields_]}
-    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ask.h"', 'int main(void) {']
+              "ask_server_cfg": [f for f, _ in ask.ask_server_cfg._fields_],
+              "ask_volume": [f for f, _ in ask.ask_volume._fields_],
+              "ask3_params": [f for f, _ in ask.ask3_params._fields_],
+              "ask3_stats": [f for f, _ in ask.ask3_stats._fields_]}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ask.h"', '#include "ask3d.h"',
+             'int main(void) {']
     for s, fs in fields.items():
         lines.append('printf("%s %%zu\\n", sizeof(%s));' % (s, s))
         for f in fs:
@@ -116,3 +123,35 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert int(got[s]) == ctypes.sizeof(cls), s
         for f in fs:
             assert int(got["%s.%s" % (s, f)]) == getattr(cls, f).offset, (s, f)
+
+
+def test_volume_validation(ask):
+    from workloads import Volume
+    good = ask.volume(Volume(-1, 1, -1, 1, -1, 1, 40, 30, 20, 100))
+    assert ask.ask3_validate(good) == 0
+    assert ask.ask3_validate(good, ask.params3(4, 2, 4)) == 0
+    assert ask.ask3_validate(good, ask.params3(4, 2, 4, "morton")) == 0
+    for g, r, B, c in [(0, 2, 4, 0), (1025, 2, 4, 0), (4, 1, 4, 0), (4, 17, 4, 0), (4, 2, 0, 0),
+                       (4, 2, 4, 2)]:
+        assert ask.ask3_validate(good, ask.params3(g, r, B, c)) == ask.EINVAL, (g, r, B, c)
+    for v in [Volume(1, -1, -1, 1, -1, 1, 8, 8, 8, 10), Volume(-1, 1, -1, 1, -1, 1, 8, 0, 8, 10),
+              Volume(-1, 1, -1, 1, -1, 1, 8, 8, 8, 0), Volume(-1, 1, -1, 1, -1, 1, 8, 8, 65537, 10),
+              Volume(-1, 1, -1, 1, -1, 1, 4096, 4096, 256, 10),
+              Volume(-1, 1, -1, 1, -1, 1, 8, 8, 8, 10, c=(float("nan"), 0.0))]:
+        assert ask.ask3_validate(ask.volume(v)) == ask.EINVAL, v
+    # the deepest and the widest grids valid sizes reach stay within the 32 levels
+    # and the 2^21 cells per axis a Morton scalar can name: a level whose sides
+    # still exceed B has G < n, so the next grid has G < n r <= 2^20
+    for g, r in ((1, 2), (1024, 16), (1000, 16)):
+        assert ask.ask3_validate(ask.volume(Volume(-1, 1, -1, 1, -1, 1, 65536, 8, 8, 10)),
+                                 ask.params3(g, r, 1, "morton")) == 0
+
+
+def test_volume_workspace_bytes(ask):
+    from workloads import Volume
+    v = Volume(-1, 1, -1, 1, -1, 1, 40, 30, 20, 100)
+    V = 40 * 30 * 20
+    for g, r, B in [(4, 2, 4), (8, 3, 1), (1, 2, 100), (64, 2, 2)]:
+        cap = min(V, max(min(g, 40) * min(g, 30) * min(g, 20), r ** 3 * (V // (B + 1))))
+        cap = (cap + 31) // 32 * 32
+        assert ask.ask3_workspace_bytes(ask.volume(v), ask.params3(g, r, B)) == 4096 + 16 * cap
