@@ -3,8 +3,9 @@
 // subdivision volumes of the quaternion Julia set, the level tables holding
 // one space-filling-curve scalar per box (canonical or Morton order).
 //
-// One wave per box, waves walking their level's table with a grid stride, so
-// a level launch needs no count from the host: the host knows in advance the
+// One wave per box, each wave taking the next entry of its level's table by
+// ticket (one atomic per box), so a level launch needs no count from the
+// host and waves that drew cheap boxes take more: the host knows in advance the
 // last level any box can reach (the first whose cells all have sides <= B)
 // and launches that many level kernels back to back, with no read-back.
 #include <hip/hip_runtime.h>
@@ -23,13 +24,15 @@ constexpr uint32_t kWavesPer = kThreads / kLanes;
 
 // Control block, in 64-bit words: entries per level table (one more word
 // than levels: the last level's children slot), then per-level fills,
-// splits and leaves, then the overflow flag.
+// splits and leaves, the overflow flag, and per-level tickets (the next
+// table entry a wave takes).
 constexpr uint32_t kCountW = 0;
 constexpr uint32_t kFillW = 40;
 constexpr uint32_t kSplitW = kFillW + ASK3_MAX_LEVELS;
 constexpr uint32_t kLeafW = kSplitW + ASK3_MAX_LEVELS;
 constexpr uint32_t kOverW = kLeafW + ASK3_MAX_LEVELS;
-constexpr uint32_t kCtrlWords = kOverW + 8;
+constexpr uint32_t kTicketW = kOverW + 8;
+constexpr uint32_t kCtrlWords = kTicketW + ASK3_MAX_LEVELS;
 constexpr uint64_t kTableOffset = 4096;
 constexpr uint32_t kMaxCoordBits = 21;  // per axis, so that a Morton scalar fits 63 bits
 
@@ -253,11 +256,12 @@ __device__ __forceinline__ void surface_voxel(uint32_t t, uint32_t w, uint32_t h
 // (surface uniform -> fill; every side <= B -> every voxel; else split).
 __global__ __launch_bounds__(kThreads) void level3_kernel(Vol3 v, Level3 L) {
     const uint32_t lane = threadIdx.x & (kLanes - 1);
-    const uint64_t wave = (uint64_t)blockIdx.x * kWavesPer + threadIdx.x / kLanes;
-    const uint64_t waves = (uint64_t)gridDim.x * kWavesPer;
     const uint64_t count = std::min((uint64_t)L.ctrl[kCountW + L.level], L.cap);
     unsigned long long nfill = 0, nsplit = 0, nleaf = 0;
-    for (uint64_t e = wave; e < count; e += waves) {
+    for (;;) {
+        const uint64_t e = wave_base(&L.ctrl[kTicketW + L.level], 1, lane);
+        if (e >= count)
+            break;
         uint32_t p[3], lo[3], hi[3];
         scalar_cell(L.in[e], L.G, L.curve, p);
         if (!cell_box(v, L.G, p, lo, hi)) {
