@@ -2,7 +2,8 @@
 volumes of quaternion Julia sets equal the 3-D oracle's bit for bit, with the
 same per-level counts, for both curves, on ragged volumes, degenerate ones
 (one voxel, one line, one slice, g above every side) and the benchmarked
-512^3 volume; the z = 0 slice equals the library's own 2-D Julia image."""
+512^3 volume; the z = 0 slice equals the library's own 2-D Julia image; a
+render captured into a HIP graph gives the oracle's volume on every replay."""
 import numpy as np
 import pytest
 
@@ -149,3 +150,35 @@ def test_benchmarked_volume(lib3, ref3):
     for x, y, z in zip(rng.integers(0, v.W, 2000), rng.integers(0, v.H, 2000),
                        rng.integers(0, v.L, 2000)):
         assert ex[z, y, x] == ref3.voxel_dwell(v, x, y, z)
+
+
+@pytest.mark.parametrize("curve", CURVES)
+def test_graph_replays_equal_the_oracle(lib3, ref3, curve):
+    """The render allocates nothing, waits for nothing and clears its control
+    block with a kernel, so it captures into a HIP graph: every replay, with
+    an eager render on another workspace in between, gives the oracle's
+    volume."""
+    ask, torch = lib3
+    v, g, r, B = VOLUMES[4]
+    o, og, orr, oB = VOLUMES[1]
+    vol, prm = ask.volume(v), ask.params3(g, r, B, curve)
+    nb = ask.ask3_workspace_bytes(vol, prm)
+    work = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    out = torch.zeros(v.voxels, dtype=torch.int32, device="cuda")
+    want = ref3.subdiv(v, g, r, B, curve)[0]
+    want2 = ref3.subdiv(o, og, orr, oB, curve)[0]
+    s = torch.cuda.current_stream()
+    ask.ask3_dwell_subdiv(vol, prm, out.data_ptr(), work.data_ptr(), nb, s.cuda_stream)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        ask.ask3_dwell_subdiv(vol, prm, out.data_ptr(), work.data_ptr(), nb,
+                              torch.cuda.current_stream().cuda_stream)
+    for rep in range(4):
+        out.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(out, v), want), rep
+        out2, _ = gpu_subdiv(lib3, o, og, orr, oB, curve, stats=False)
+        assert np.array_equal(host(out2, o), want2), rep
+    del graph
