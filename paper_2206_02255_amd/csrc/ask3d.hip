@@ -3,9 +3,10 @@
 // subdivision volumes of the quaternion Julia set, the level tables holding
 // one space-filling-curve scalar per box (canonical or Morton order).
 //
-// One wave per box, each wave taking the next entry of its level's table by
-// ticket (one atomic per box), so a level launch needs no count from the
-// host and waves that drew cheap boxes take more: the host knows in advance the
+// One wave per box, each wave claiming the next entries of its level's table
+// by ticket (one atomic per box, or per chunk of boxes on levels with very
+// many), so a level launch needs no count from the host and waves that drew
+// cheap boxes take more: the host knows in advance the
 // last level any box can reach (the first whose cells all have sides <= B)
 // and launches that many level kernels back to back, with no read-back.
 #include <hip/hip_runtime.h>
@@ -155,6 +156,16 @@ __device__ __forceinline__ uint64_t wave_base(unsigned long long *counter, uint6
     return (uint64_t)hi << 32 | lo;
 }
 
+// Lane 0 adds n to the counter; every lane gets the counter's old value.
+__device__ __forceinline__ uint64_t wave_claim(unsigned long long *counter, uint64_t n,
+                                               uint32_t lane) {
+    uint64_t base = 0;
+    if (lane == 0)
+        base = atomicAdd(counter, (unsigned long long)n);
+    const uint32_t lo = __shfl((uint32_t)base, 0), hi = __shfl((uint32_t)(base >> 32), 0);
+    return (uint64_t)hi << 32 | lo;
+}
+
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask, uint32_t lane) {
     return (uint32_t)__popcll(mask & ((1ull << lane) - 1));
 }
@@ -257,70 +268,78 @@ __device__ __forceinline__ void surface_voxel(uint32_t t, uint32_t w, uint32_t h
 __global__ __launch_bounds__(kThreads) void level3_kernel(Vol3 v, Level3 L) {
     const uint32_t lane = threadIdx.x & (kLanes - 1);
     const uint64_t count = std::min((uint64_t)L.ctrl[kCountW + L.level], L.cap);
+    // Entries per claim: one while the level has few boxes per wave (the best
+    // balance), up to 64 when it has very many small ones, so that the one
+    // counter address does not serialise the level.
+    const uint64_t waves = (uint64_t)gridDim.x * kWavesPer;
+    const uint64_t chunk = std::max<uint64_t>(1, std::min<uint64_t>(64, count / (waves * 16)));
     unsigned long long nfill = 0, nsplit = 0, nleaf = 0;
     for (;;) {
-        const uint64_t e = wave_base(&L.ctrl[kTicketW + L.level], 1, lane);
-        if (e >= count)
+        const uint64_t e0 = wave_claim(&L.ctrl[kTicketW + L.level], chunk, lane);
+        if (e0 >= count)
             break;
-        uint32_t p[3], lo[3], hi[3];
-        scalar_cell(L.in[e], L.G, L.curve, p);
-        if (!cell_box(v, L.G, p, lo, hi)) {
-            if (lane == 0)
-                atomicOr(&L.ctrl[kOverW], 2ull);
-            continue;
-        }
-        const uint32_t w = hi[0] - lo[0], h = hi[1] - lo[1], l = hi[2] - lo[2];
-        const uint32_t first = voxel_dwell(v, lo[0], lo[1], lo[2]);
-        const uint32_t S = surface_count(w, h, l);
-        bool uniform = true;
-        for (uint32_t t0 = 0; t0 < S; t0 += kLanes) {
-            const uint32_t t = t0 + lane;
-            bool differs = false;
-            if (t < S) {
-                uint32_t x, y, z;
-                surface_voxel(t, w, h, l, x, y, z);
-                differs = voxel_dwell(v, lo[0] + x, lo[1] + y, lo[2] + z) != first;
+        const uint64_t e1 = std::min(e0 + chunk, count);
+        for (uint64_t e = e0; e < e1; ++e) {
+            uint32_t p[3], lo[3], hi[3];
+            scalar_cell(L.in[e], L.G, L.curve, p);
+            if (!cell_box(v, L.G, p, lo, hi)) {
+                if (lane == 0)
+                    atomicOr(&L.ctrl[kOverW], 2ull);
+                continue;
             }
-            if (__ballot(differs)) {
-                uniform = false;
-                break;
-            }
-        }
-        const uint32_t wh = w * h, n = wh * l;
-        if (uniform) {
-            for (uint32_t t = lane; t < n; t += kLanes)
-                put_voxel(v, lo[0] + t % w, lo[1] + (t / w) % h, lo[2] + t / wh, first);
-            ++nfill;
-        } else if (w <= L.B && h <= L.B && l <= L.B) {
-            for (uint32_t t = lane; t < n; t += kLanes) {
-                const uint32_t x = lo[0] + t % w, y = lo[1] + (t / w) % h, z = lo[2] + t / wh;
-                put_voxel(v, x, y, z, voxel_dwell(v, x, y, z));
-            }
-            ++nleaf;
-        } else {
-            const uint32_t r = L.r, kids = r * r * r;
-            const uint64_t G1 = L.G * r;
-            for (uint32_t k0 = 0; k0 < kids; k0 += kLanes) {
-                const uint32_t k = k0 + lane;
-                uint32_t c[3] = {0, 0, 0}, clo[3], chi[3];
-                bool ok = false;
-                if (k < kids) {
-                    c[0] = p[0] * r + k % r;
-                    c[1] = p[1] * r + (k / r) % r;
-                    c[2] = p[2] * r + k / (r * r);
-                    ok = cell_box(v, G1, c, clo, chi);
+            const uint32_t w = hi[0] - lo[0], h = hi[1] - lo[1], l = hi[2] - lo[2];
+            const uint32_t first = voxel_dwell(v, lo[0], lo[1], lo[2]);
+            const uint32_t S = surface_count(w, h, l);
+            bool uniform = true;
+            for (uint32_t t0 = 0; t0 < S; t0 += kLanes) {
+                const uint32_t t = t0 + lane;
+                bool differs = false;
+                if (t < S) {
+                    uint32_t x, y, z;
+                    surface_voxel(t, w, h, l, x, y, z);
+                    differs = voxel_dwell(v, lo[0] + x, lo[1] + y, lo[2] + z) != first;
                 }
-                const uint64_t mask = __ballot(ok);
-                const uint64_t base = wave_base(&L.ctrl[kCountW + L.level + 1], mask, lane);
-                if (ok) {
-                    const uint64_t at = base + lanes_below(mask, lane);
-                    if (at < L.cap)
-                        L.next[at] = cell_scalar(c, G1, L.curve);
-                    else
-                        atomicOr(&L.ctrl[kOverW], 1ull);
+                if (__ballot(differs)) {
+                    uniform = false;
+                    break;
                 }
             }
-            ++nsplit;
+            const uint32_t wh = w * h, n = wh * l;
+            if (uniform) {
+                for (uint32_t t = lane; t < n; t += kLanes)
+                    put_voxel(v, lo[0] + t % w, lo[1] + (t / w) % h, lo[2] + t / wh, first);
+                ++nfill;
+            } else if (w <= L.B && h <= L.B && l <= L.B) {
+                for (uint32_t t = lane; t < n; t += kLanes) {
+                    const uint32_t x = lo[0] + t % w, y = lo[1] + (t / w) % h, z = lo[2] + t / wh;
+                    put_voxel(v, x, y, z, voxel_dwell(v, x, y, z));
+                }
+                ++nleaf;
+            } else {
+                const uint32_t r = L.r, kids = r * r * r;
+                const uint64_t G1 = L.G * r;
+                for (uint32_t k0 = 0; k0 < kids; k0 += kLanes) {
+                    const uint32_t k = k0 + lane;
+                    uint32_t c[3] = {0, 0, 0}, clo[3], chi[3];
+                    bool ok = false;
+                    if (k < kids) {
+                        c[0] = p[0] * r + k % r;
+                        c[1] = p[1] * r + (k / r) % r;
+                        c[2] = p[2] * r + k / (r * r);
+                        ok = cell_box(v, G1, c, clo, chi);
+                    }
+                    const uint64_t mask = __ballot(ok);
+                    const uint64_t base = wave_base(&L.ctrl[kCountW + L.level + 1], mask, lane);
+                    if (ok) {
+                        const uint64_t at = base + lanes_below(mask, lane);
+                        if (at < L.cap)
+                            L.next[at] = cell_scalar(c, G1, L.curve);
+                        else
+                            atomicOr(&L.ctrl[kOverW], 1ull);
+                    }
+                }
+                ++nsplit;
+            }
         }
     }
     if (lane == 0) {
