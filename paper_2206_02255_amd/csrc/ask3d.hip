@@ -290,17 +290,25 @@ __global__ __launch_bounds__(kThreads) void level3_kernel(Vol3 v, Level3 L) {
             const uint32_t w = hi[0] - lo[0], h = hi[1] - lo[1], l = hi[2] - lo[2];
             const uint32_t first = voxel_dwell(v, lo[0], lo[1], lo[2]);
             const uint32_t S = surface_count(w, h, l);
+            const bool leaf_size = w <= L.B && h <= L.B && l <= L.B;
+            // The scan writes every surface dwell it computes, so a leaf box only
+            // finishes the surface from where the scan stopped and adds its interior.
             bool uniform = true;
-            for (uint32_t t0 = 0; t0 < S; t0 += kLanes) {
+            uint32_t t0 = 0;
+            for (; t0 < S; t0 += kLanes) {
                 const uint32_t t = t0 + lane;
                 bool differs = false;
                 if (t < S) {
                     uint32_t x, y, z;
                     surface_voxel(t, w, h, l, x, y, z);
-                    differs = voxel_dwell(v, lo[0] + x, lo[1] + y, lo[2] + z) != first;
+                    const uint32_t d = voxel_dwell(v, lo[0] + x, lo[1] + y, lo[2] + z);
+                    if (leaf_size)
+                        put_voxel(v, lo[0] + x, lo[1] + y, lo[2] + z, d);
+                    differs = d != first;
                 }
                 if (__ballot(differs)) {
                     uniform = false;
+                    t0 += kLanes;
                     break;
                 }
             }
@@ -309,9 +317,20 @@ __global__ __launch_bounds__(kThreads) void level3_kernel(Vol3 v, Level3 L) {
                 for (uint32_t t = lane; t < n; t += kLanes)
                     put_voxel(v, lo[0] + t % w, lo[1] + (t / w) % h, lo[2] + t / wh, first);
                 ++nfill;
-            } else if (w <= L.B && h <= L.B && l <= L.B) {
-                for (uint32_t t = lane; t < n; t += kLanes) {
-                    const uint32_t x = lo[0] + t % w, y = lo[1] + (t / w) % h, z = lo[2] + t / wh;
+            } else if (leaf_size) {
+                for (uint32_t t = t0 + lane; t < S; t += kLanes) {
+                    uint32_t x, y, z;
+                    surface_voxel(t, w, h, l, x, y, z);
+                    put_voxel(v, lo[0] + x, lo[1] + y, lo[2] + z,
+                              voxel_dwell(v, lo[0] + x, lo[1] + y, lo[2] + z));
+                }
+                // interior: (w - 2) x (h - 2) x (l - 2), empty when the box is all surface
+                const uint32_t iw = w > 2 ? w - 2 : 0, ih = h > 2 ? h - 2 : 0,
+                               il = l > 2 ? l - 2 : 0;
+                const uint32_t iwh = iw * ih, in = iwh * il;
+                for (uint32_t t = lane; t < in; t += kLanes) {
+                    const uint32_t x = lo[0] + 1 + t % iw, y = lo[1] + 1 + (t / iw) % ih,
+                                   z = lo[2] + 1 + t / iwh;
                     put_voxel(v, x, y, z, voxel_dwell(v, x, y, z));
                 }
                 ++nleaf;
