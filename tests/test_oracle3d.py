@@ -125,6 +125,71 @@ def test_y_z_exchange_for_real_c(ref3):
     assert not np.array_equal(E2, E2.transpose(1, 0, 2))
 
 
+# The binary64 operation order of the quaternion step (the reading taken:
+# a2 = a*a, b2 = b*b, e2 = e*e, ab = a*b, ae = a*e; a = (a2 - (b2 + e2)) + cr;
+# b = (ab + ab) + ci; e = (ae + ae) + 0; escape when a*a + (b*b + e*e) > 4;
+# each operation rounded on its own), evaluated independently with numpy
+# binary64 arrays, one ufunc call per operation, over volumes where long
+# escaping orbits make a reassociated or contracted step change dwells.
+def binary64_volume(v):
+    axes = []
+    for lo, hi, n in ((v.x0, v.x1, v.W), (v.y0, v.y1, v.H), (v.z0, v.z1, v.L)):
+        centre = 0.5 * (lo + hi)
+        half = (hi - lo) / (2.0 * n)
+        k = (2 * np.arange(n, dtype=np.int64) + 1 - n).astype(np.float64)
+        axes.append(centre + np.multiply(k, half))
+    shape = (v.L, v.H, v.W)
+    a = np.broadcast_to(axes[0][None, None, :], shape).ravel().copy()
+    b = np.broadcast_to(axes[1][None, :, None], shape).ravel().copy()
+    e = np.broadcast_to(axes[2][:, None, None], shape).ravel().copy()
+    cr, ci = float(v.c[0]), float(v.c[1])
+    out = np.full(a.size, v.D, dtype=np.int64)
+    idx = np.arange(a.size)
+    with np.errstate(over="ignore", invalid="ignore"):
+        for k in range(1, v.D + 1):
+            a2 = np.multiply(a, a)
+            b2 = np.multiply(b, b)
+            e2 = np.multiply(e, e)
+            ab = np.multiply(a, b)
+            ae = np.multiply(a, e)
+            a = np.add(np.subtract(a2, np.add(b2, e2)), cr)
+            b = np.add(np.add(ab, ab), ci)
+            e = np.add(np.add(ae, ae), 0.0)
+            mag = np.add(np.multiply(a, a), np.add(np.multiply(b, b), np.multiply(e, e)))
+            esc = mag > 4.0
+            if esc.any():
+                out[idx[esc]] = k
+                keep = ~esc
+                idx, a, b, e = idx[keep], a[keep], b[keep], e[keep]
+                if idx.size == 0:
+                    break
+    return out.reshape(shape)
+
+
+OP_ORDER_VOLUMES = [
+    # a Cantor dust: every orbit escapes, the whole volume is near the set
+    Volume(-1.6, 1.6, -1.0, 1.0, -1.0, 1.0, 64, 48, 48, 2000, c=(-0.8, 0.156)),
+    Volume(-1.6, 1.6, -1.0, 1.0, -0.5, 0.5, 64, 40, 32, 1000, c=(-0.8, 0.156)),
+    # the benchmark's c, and a c near the parabolic point -3/4
+    Volume(-1.6, 1.6, -1.6, 1.6, -1.6, 1.6, 48, 48, 48, 256, c=(-0.2, 0.6)),
+    Volume(-1.2, 1.2, -0.8, 0.8, 0.0, 0.8, 64, 48, 24, 2000, c=(-0.75, 0.1)),
+]
+
+
+@pytest.mark.parametrize("v", OP_ORDER_VOLUMES,
+                         ids=lambda v: "c%g_%g_%dx%dx%d" % (v.c[0], v.c[1], v.W, v.H, v.L))
+def test_operation_order_binary64(ref3, v):
+    got = ref3.exhaustive(v)
+    want = binary64_volume(v)
+    diff = np.argwhere(got != want)
+    assert diff.size == 0, "3-D oracle differs from the binary64 reading at %d voxels, first %s" % (
+        len(diff), diff[:5].tolist())
+
+
+def test_op_order_volumes_cover_enough_voxels():
+    assert sum(v.voxels for v in OP_ORDER_VOLUMES) >= 300000
+
+
 def test_voxel_dwell_equals_volume(ref3):
     v = Volume(-1.6, 1.6, -1.6, 1.6, -1.0, 1.4, 20, 17, 13, 150, c=(-0.2, 0.6))
     E = ref3.exhaustive(v)
@@ -300,6 +365,7 @@ def test_bad_arguments(ref3):
 
 SRC = os.path.join(ROOT, "oracle", "askref3.c")
 PINS = ["test_zero_slice_is_the_julia_image", "test_c_zero_closed_form",
+        "test_operation_order_binary64",
         "test_volume_c_zero_closed_form",
         "test_mirror_in_z", "test_y_z_exchange_for_real_c", "test_canonical_curve",
         "test_morton_curve", "test_level_grids_nest", "test_subdivision_follows_the_rule",
@@ -322,18 +388,30 @@ MUTANTS = {
                                "uint64_t G1 = G * r + 1, n1 = 0, cap1 = 0;"),
     "ceil_partition": ("return (uint32_t)(j * (uint64_t)n / G);",
                        "return (uint32_t)((j * (uint64_t)n + G - 1) / G);"),
+    # binary64 operation order of the quaternion step
+    "reassoc_a_part": ("a = (a2 - (b2 + e2)) + cr;", "a = ((a2 - b2) - e2) + cr;"),
+    "reassoc_b_part": ("b = (ab + ab) + ci;", "b = ab + (ab + ci);"),
 }
+
+# The unchanged source built with contraction into fused multiply-adds.
+FLAG_MUTANTS = {"contracted_build": ("-ffp-contract=fast", "-mfma")}
 
 
 @pytest.mark.slow
 def test_every_planted_mistake_is_caught(tmp_path):
     src = open(SRC).read()
     escaped = []
-    for name, (a, b) in MUTANTS.items():
-        assert src.count(a) == 1, name
+    for name in list(MUTANTS) + list(FLAG_MUTANTS):
+        text, extra = src, ("-Wno-error",)
+        if name in FLAG_MUTANTS:
+            extra += FLAG_MUTANTS[name]
+        else:
+            a, b = MUTANTS[name]
+            assert src.count(a) == 1, name
+            text = src.replace(a, b)
         path = tmp_path / ("m_%s.c" % name)
-        path.write_text(src.replace(a, b))
-        lib = oracle_build.build(extra=("-Wno-error",), src=str(path),
+        path.write_text(text)
+        lib = oracle_build.build(extra=extra, src=str(path),
                                  out=str(tmp_path / ("lib_%s.so" % name)))
         env = dict(os.environ, ASKREF3_LIB=lib)
         p = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",

@@ -185,3 +185,169 @@ def test_bad_windows_rejected(ref):
               Window(-1, 1, -1, 1, 65537, 8, 10)]:
         with pytest.raises(ValueError):
             ref.exhaustive(w)
+
+
+# --------------------------------------------------------------------------
+# The binary64 operation order (the paper fixes no order; the reading taken:
+# per iteration zr2 = zr*zr, zi2 = zi*zi, zri = zr*zi, zr = (zr2 - zi2) + cr,
+# zi = (zri + zri) + ci, escape when zr*zr + zi*zi > 4, every operation
+# rounded on its own, no fused multiply-add). The exact-arithmetic pins above
+# cannot see the rounding order: they skip every orbit that passes near the
+# escape circle. These pins evaluate the same reading independently, with
+# numpy binary64 arrays (each ufunc call is one correctly rounded operation;
+# numpy never fuses two calls) and, on a subset, with Python floats, over
+# windows chosen so that a reassociated or contracted evaluation changes
+# dwells: orbits near c = -2 and |c| = 2, where |z|^2 sits on 4 for many
+# iterations, and long orbits near the boundary, where a one-ulp difference
+# grows until it moves the escape.
+# --------------------------------------------------------------------------
+
+def binary64_points(w):
+    """Pixel points of a window in binary64, in the order of the mapping
+    reading: centre, half pitch, then centre + (2p + 1 - N) * half pitch."""
+    cxm = 0.5 * (w.x0 + w.x1)
+    cym = 0.5 * (w.y0 + w.y1)
+    hx = (w.x1 - w.x0) / (2.0 * w.W)
+    hy = (w.y1 - w.y0) / (2.0 * w.H)
+    kx = (2 * np.arange(w.W, dtype=np.int64) + 1 - w.W).astype(np.float64)
+    ky = (2 * np.arange(w.H, dtype=np.int64) + 1 - w.H).astype(np.float64)
+    pr = cxm + np.multiply(kx, hx)
+    pi = cym + np.multiply(ky, hy)
+    return np.broadcast_to(pr[None, :], (w.H, w.W)), np.broadcast_to(pi[:, None], (w.H, w.W))
+
+
+def binary64_dwells(zr, zi, cr, ci, D):
+    """Dwells of orbits started at z0 = (zr, zi) with constants (cr, ci)
+    (arrays of one shape, or scalars broadcast to it), evaluated with one
+    numpy operation per binary64 operation of the reading; lanes leave the
+    arrays as they escape."""
+    zr, zi, cr, ci = np.broadcast_arrays(*(np.asarray(a, dtype=np.float64)
+                                           for a in (zr, zi, cr, ci)))
+    shape = zr.shape
+    zr, zi = zr.ravel().copy(), zi.ravel().copy()
+    cr, ci = cr.ravel().copy(), ci.ravel().copy()
+    out = np.full(zr.size, D, dtype=np.int64)
+    np.seterr(over="ignore", invalid="ignore")  # escaped orbits may overflow; they leave
+    idx = np.arange(zr.size)
+    for k in range(1, D + 1):
+        zr2 = np.multiply(zr, zr)
+        zi2 = np.multiply(zi, zi)
+        zri = np.multiply(zr, zi)
+        zr = np.add(np.subtract(zr2, zi2), cr)
+        zi = np.add(np.add(zri, zri), ci)
+        mag = np.add(np.multiply(zr, zr), np.multiply(zi, zi))
+        esc = mag > 4.0
+        if esc.any():
+            out[idx[esc]] = k
+            keep = ~esc
+            idx, zr, zi, cr, ci = idx[keep], zr[keep], zi[keep], cr[keep], ci[keep]
+            if idx.size == 0:
+                break
+    return out.reshape(shape)
+
+
+def python_float_dwell(zr, zi, cr, ci, D):
+    """The same reading with Python floats (IEEE binary64, never fused)."""
+    zr, zi, cr, ci = float(zr), float(zi), float(cr), float(ci)
+    for k in range(1, D + 1):
+        zr2 = zr * zr
+        zi2 = zi * zi
+        zri = zr * zi
+        zr = (zr2 - zi2) + cr
+        zi = (zri + zri) + ci
+        if zr * zr + zi * zi > 4.0:
+            return k
+    return D
+
+
+def _deep_window(n, D):
+    from workloads import deep_window
+    return deep_window(n=n, D=D)
+
+
+# Windows of the op-order pins: 9 windows, 1.3e5 pixels in all.
+OP_ORDER_WINDOWS = [
+    # c = -2 and its neighbourhood: the orbit 0, -2, 2, 2, ... has |z|^2 = 4.
+    Window(-2.0 - 3e-6, -2.0 + 3e-6, -3e-6, 3e-6, 96, 96, 3000),
+    # across the circle |c| = 2 at two angles (|z_1|^2 = |c|^2 on 4)
+    Window(-1.4142135623730951 - 2e-3, -1.4142135623730951 + 2e-3,
+           1.4142135623730951 - 2e-3, 1.4142135623730951 + 2e-3, 96, 96, 2000),
+    Window(1.9999, 2.0001, -1e-4, 1e-4, 64, 64, 500),
+    # the boundary of the paper's window, seahorse valley and a deep spiral
+    Window(-0.7465, -0.7445, 0.1025, 0.1045, 128, 128, 4000),
+    Window(-1.5, 0.5, -1.0, 1.0, 128, 128, 2048),
+    # the deep-zoom window (width 1e-6 around a stored boundary point, D = 8192)
+    "deep",
+    # filled Julia sets: basilica, rabbit, Cantor dust
+    Window(-1.7, 1.7, -1.7, 1.7, 128, 128, 2048, julia=(-1.0, 0.0)),
+    Window(-0.4, -0.2, 0.45, 0.65, 96, 96, 3000, julia=(-0.123, 0.745)),
+    Window(-1.6, 1.6, -1.0, 1.0, 128, 96, 1000, julia=(-0.8, 0.156)),
+]
+
+
+def _op_window(w):
+    return _deep_window(160, 8192) if w == "deep" else w
+
+
+@pytest.mark.parametrize("w", OP_ORDER_WINDOWS, ids=lambda w: w if isinstance(w, str) else
+                         "%g_%g_%dx%d" % (w.x0, w.y0, w.W, w.H))
+def test_operation_order_binary64(ref, w):
+    w = _op_window(w)
+    img, iters = ref.exhaustive(w)
+    pr, pi = binary64_points(w)
+    if w.julia is None:
+        want = binary64_dwells(0.0, 0.0, pr, pi, w.D)
+    else:
+        want = binary64_dwells(pr, pi, w.julia[0], w.julia[1], w.D)
+    diff = np.argwhere(img != want)
+    assert diff.size == 0, "oracle differs from the binary64 reading at %d pixels, first %s" % (
+        len(diff), diff[:5].tolist())
+    assert iters == int(want.sum())
+
+
+def test_op_order_windows_cover_enough_pixels():
+    n = sum(_op_window(w).pixels for w in OP_ORDER_WINDOWS)
+    assert n >= 100000, n
+
+
+def test_op_order_windows_are_rounding_sensitive():
+    # The windows above must tell the reading apart from its nearest
+    # alternatives; otherwise matching them would pin nothing. Evaluated
+    # here with numpy, with the alternative written out: the real part
+    # reassociated as zr2 - (zi2 - cr).
+    changed = 0
+    np.seterr(over="ignore", invalid="ignore")
+    for w in OP_ORDER_WINDOWS[:5]:
+        w = _op_window(w)
+        pr, pi = binary64_points(w)
+        a = binary64_dwells(0.0, 0.0, pr, pi, w.D)
+        zr = np.zeros(pr.shape)
+        zi = np.zeros(pr.shape)
+        out = np.full(pr.shape, w.D, dtype=np.int64)
+        live = np.ones(pr.shape, dtype=bool)
+        for k in range(1, w.D + 1):
+            zr2, zi2, zri = zr * zr, zi * zi, zr * zi
+            zr = zr2 - (zi2 - pr)
+            zi = (zri + zri) + pi
+            esc = live & (zr * zr + zi * zi > 4.0)
+            out[esc] = k
+            live &= ~esc
+            if not live.any():
+                break
+        changed += int((out != a).sum())
+    assert changed > 0
+
+
+def test_operation_order_python_floats(ref):
+    # Python floats on random points of three sensitive windows, through the
+    # oracle's single-point entry points.
+    rng = np.random.default_rng(41)
+    for w in (OP_ORDER_WINDOWS[0], OP_ORDER_WINDOWS[3], OP_ORDER_WINDOWS[7]):
+        for _ in range(300):
+            x = float(rng.uniform(w.x0, w.x1))
+            y = float(rng.uniform(w.y0, w.y1))
+            if w.julia is None:
+                assert ref.dwell(x, y, w.D) == python_float_dwell(0.0, 0.0, x, y, w.D), (x, y)
+            else:
+                assert ref.dwell_julia(x, y, *w.julia, w.D) == python_float_dwell(
+                    x, y, w.julia[0], w.julia[1], w.D), (x, y)

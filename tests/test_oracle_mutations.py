@@ -48,6 +48,18 @@ MUTANTS = {
     "julia_set_ignored": ("if (set && set->julia)", "if (set && !set->julia)"),
     "ring_new_counts_parent_ring": ("if (R->pw == 0 || !on_ring(R->px, R->py, R->pw, R->ph, px, py))",
                                     "if (R->pw == 0 || on_ring(R->px, R->py, R->pw, R->ph, px, py))"),
+    # binary64 operation order: one reassociation in each part of z^2 + c
+    "reassoc_real": ("zr = (zr2 - zi2) + cr;", "zr = zr2 - (zi2 - cr);"),
+    "reassoc_imag": ("zi = (zri + zri) + ci;", "zi = zri + (zri + ci);"),
+    "reassoc_real_c_first": ("zr = (zr2 - zi2) + cr;", "zr = (zr2 + cr) - zi2;"),
+    # the real part as a product of sum and difference, a common rewriting
+    "factored_real_part": ("zr = (zr2 - zi2) + cr;", "zr = (zr + zi) * (zr - zi) + cr;"),
+}
+
+# Builds of the unchanged source with other compiler flags: contraction into
+# fused multiply-adds changes the rounding of every iteration.
+FLAG_MUTANTS = {
+    "contracted_build": ("-ffp-contract=fast", "-mfma"),
 }
 
 PIN_TESTS = ["tests/test_oracle_dwell.py", "tests/test_oracle_subdiv.py",
@@ -55,13 +67,19 @@ PIN_TESTS = ["tests/test_oracle_dwell.py", "tests/test_oracle_subdiv.py",
 
 
 def run_mutant(name, tmpdir):
-    old, new = MUTANTS[name]
     text = open(SRC).read()
-    assert text.count(old) == 1, name
+    extra = ("-Wno-error",)  # a planted mistake may leave a value unused
+    if name in FLAG_MUTANTS:
+        extra += FLAG_MUTANTS[name]
+    else:
+        old, new = MUTANTS[name]
+        assert text.count(old) == 1, name
+        text = text.replace(old, new)
     src = os.path.join(tmpdir, "askref_%s.c" % name)
     with open(src, "w") as f:
-        f.write(text.replace(old, new))
-    lib = oracle_build.build(src=src, out=os.path.join(tmpdir, "libaskref_%s.so" % name))
+        f.write(text)
+    lib = oracle_build.build(extra=extra, src=src,
+                             out=os.path.join(tmpdir, "libaskref_%s.so" % name))
     env = dict(os.environ, ASKREF_LIB=lib)
     p = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:randomly",
                         "-k", "not brute_force", *PIN_TESTS],
@@ -71,6 +89,7 @@ def run_mutant(name, tmpdir):
 
 def test_every_planted_mistake_is_caught(tmp_path):
     with ThreadPoolExecutor(max_workers=4) as ex:
-        results = list(ex.map(lambda n: run_mutant(n, str(tmp_path)), sorted(MUTANTS)))
+        results = list(ex.map(lambda n: run_mutant(n, str(tmp_path)),
+                              sorted(MUTANTS) + sorted(FLAG_MUTANTS)))
     survived = [name for name, rc in results if rc == 0]
     assert not survived, "pins missed planted mistakes: %s" % survived
