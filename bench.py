@@ -41,22 +41,27 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2206_02255_amd", "csrc", f)
                   for f in ("ask_kernels.hip", "ask_internal.hpp")]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the persistent kernel from the committed
-    counter runs, or None when the kernel sources have changed since."""
+def kernel_source_hash():
     import hashlib
-    try:
-        fields = dict(line.split(": ", 1) for line in open(PROFILE).read().splitlines()
-                      if line.startswith(("traffic_bytes_per_launch:", "kernel_source_sha256:")))
-    except (OSError, ValueError):
-        return None
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(f, "rb") as fh:
             h.update(fh.read())
-    if fields.get("kernel_source_sha256", "").strip() != h.hexdigest():
+    return h.hexdigest()
+
+
+def profiled(key):
+    """A per-launch figure of the persistent kernel from the committed counter
+    runs (HBM traffic, FP64 instructions), or None when the kernel sources
+    have changed since they were taken."""
+    try:
+        fields = dict(line.split(": ", 1) for line in open(PROFILE).read().splitlines()
+                      if line.startswith((key + ":", "kernel_source_sha256:")))
+    except (OSError, ValueError):
         return None
-    return int(fields["traffic_bytes_per_launch"])
+    if fields.get("kernel_source_sha256", "").strip() != kernel_source_hash() or key not in fields:
+        return None
+    return int(fields[key])
 
 
 def log(msg):
@@ -88,64 +93,84 @@ def parse():
     return ap.parse_args()
 
 
-def batched_leg(ctx, torch, ask, workloads, sp, count, steps):
-    """The batched workload in one persistent launch per step, and the same
+def batched_leg(ctx, torch, ask, autotune, workloads, sp, count, steps):
+    """The batched workload (256 boundary images) captured whole into a HIP
+    graph and replayed, one persistent launch per replay, with the per-image
+    (g, r, B) rule and wave tile the autotuner chose for it; against the same
     images rendered one at a time (persistent, then per-level form)."""
     import numpy as np
     ims = workloads.batch_images(count=count)
-    prms = [workloads.batch_params(w.W) for w in ims]
+    hit = autotune.lookup(autotune.BATCH_KEY) if count == 256 else None
+    rule = hit["rule"] if hit else {"s0": 256, "r": 2, "B": 128, "tile": [0, 0]}
+    prms = [workloads.rule_params(w.W, rule["s0"], rule["r"], rule["B"]) for w in ims]
+    tile = tuple(rule["tile"])
     sizes = [w.pixels for w in ims]
     total = sum(sizes)
     offs = np.concatenate([[0], np.cumsum(sizes)[:-1]])
     out = torch.empty(total, dtype=torch.int32, device="cuda")
     ptrs = [out.data_ptr() + 4 * int(o) for o in offs]
     wins = [ask.window(w) for w in ims]
-    pers = [ask.params(p.g, p.r, p.B, "persistent") for p in prms]
-    log("batched: %d images, %.2f Gpix; counting pass" % (count, total / 1e9))
+    pers = [ask.params(p.g, p.r, p.B, "persistent", 0, tile) for p in prms]
+    log("batched: %d images, %.2f Gpix, rule %s; counting pass" % (count, total / 1e9, rule))
     st = ask.ask_dwell_batch(ctx, wins, pers, ptrs, sp, want_stats=True)
     iters = st["iters_ring"] + st["iters_leaf"]
+    eager_img = out.clone()
+    # The whole batch as one graph: image table, counter reset, queue clear,
+    # seeding and the persistent kernel.
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        ask.ask_dwell_batch(ctx, wins, pers, ptrs, torch.cuda.current_stream().cuda_stream)
+    log("batched: captured")
+    replay_stream = torch.cuda.current_stream()
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    out.zero_()
+    graph.replay()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    marks[0].record(replay_stream)
     for k in range(steps):
-        ask.ask_dwell_batch(ctx, wins, pers, ptrs, sp)
-        torch.cuda.synchronize()
-        log("batched: step %d of %d done" % (k + 1, steps))
+        graph.replay()
+        marks[k + 1].record(replay_stream)
+    torch.cuda.synchronize()
     ms = 1e3 * (time.perf_counter() - t0) / steps
+    replay_ms = sorted(marks[k].elapsed_time(marks[k + 1]) for k in range(steps))
+    kms = replay_ms[len(replay_ms) // 2]
+    replay_same = bool(torch.equal(out, eager_img))
+    log("batched: %d replays done" % steps)
     ask.ask_synchronize(ctx, sp)
-    ask.ask_enable_timing(ctx, True)
-    ask.ask_dwell_batch(ctx, wins, pers, ptrs, sp)
-    kms = ask.ask_last_kernel_ms(ctx)
-    ask.ask_enable_timing(ctx, False)
-    batch_img = out.clone()
+    del graph
 
-    def one_by_one(form, params):
+    def one_by_one(form, params, tile_=(0, 0)):
         torch.cuda.synchronize()
         t = time.perf_counter()
         for w, p, ptr in zip(wins, params, ptrs):
-            ask.ask_dwell_subdiv(ctx, w, ask.params(p.g, p.r, p.B, form), ptr, sp)
+            ask.ask_dwell_subdiv(ctx, w, ask.params(p.g, p.r, p.B, form, 0, tile_), ptr, sp)
         torch.cuda.synchronize()
         ask.ask_synchronize(ctx, sp)
         return 1e3 * (time.perf_counter() - t)
 
     # The same images and parameters one at a time must give the batch's images.
-    seq_pers_ms = one_by_one("persistent", prms)
+    seq_pers_ms = one_by_one("persistent", prms, tile)
     log("batched: one by one (persistent) done")
-    same = bool(torch.equal(out, batch_img))
-    seq_lv_same_ms = one_by_one("levels", prms)
+    same = bool(torch.equal(out, eager_img))
+    seq_lv_same_ms = one_by_one("levels", prms, tile)
     log("batched: one by one (levels, same parameters) done")
-    same = same and bool(torch.equal(out, batch_img))
+    same = same and bool(torch.equal(out, eager_img))
     # The per-level form also with smaller leaves (B = 32); its baseline is the
     # faster of the two.
     lv_prms = [workloads.batch_params_levels(w.W) for w in ims]
     seq_lv_small_ms = one_by_one("levels", lv_prms)
     log("batched: one by one (levels, B = 32) done")
     seq_lv_ms = min(seq_lv_same_ms, seq_lv_small_ms)
-    del out, batch_img
+    del out, eager_img
     return {"workload": "batch-%d-boundary-images" % count, "images": count, "pixels": total,
+            "rule": rule, "params_source": "autotuner cache" if hit else "default",
+            "graph_replay": True,
             "ms": round(ms, 3), "mpix_s": round(total / (ms * 1e-3) / 1e6, 1),
-            "kernel_ms": round(kms, 3), "dwell_iterations": iters,
+            "replay_ms_median": round(kms, 3), "dwell_iterations": iters,
             "fp64_frac": round(FLOPS_PER_ITERATION * iters / (kms * 1e-3) / 1e12
                                / PEAK_FP64_TFLOPS, 4),
+            "replays_equal_eager_batch": replay_same,
             "one_by_one_persistent_ms": round(seq_pers_ms, 3),
             "one_by_one_levels_ms": round(seq_lv_ms, 3),
             "one_by_one_levels_same_params_ms": round(seq_lv_same_ms, 3),
@@ -154,39 +179,51 @@ def batched_leg(ctx, torch, ask, workloads, sp, count, steps):
             "equals_one_by_one": same}
 
 
-def deep_leg(ctx, torch, ask, workloads, sp):
+def deep_leg(ctx, torch, ask, autotune, workloads, sp):
     """The deep-zoom image (32768^2, width 1e-6 around a boundary point,
-    D = 8192): exhaustive kernel, persistent and per-level subdivision."""
+    D = 8192) with the autotuner's choice for its class: exhaustive kernel,
+    persistent and per-level subdivision."""
     w = workloads.deep_window()
-    p = workloads.DEEP_PARAMS
     win = ask.window(w)
+    hit = autotune.lookup(autotune.workload_key(win, "persistent"))
+    if hit and "tile" in hit:
+        g, r, B, tile, ex_tile = hit["g"], hit["r"], hit["B"], tuple(hit["tile"]), tuple(
+            hit["exhaustive_tile"])
+    else:
+        p = workloads.DEEP_PARAMS
+        g, r, B, tile, ex_tile = p.g, p.r, p.B, (0, 0), (16, 4)
     out = torch.empty(w.W * w.H, dtype=torch.int32, device="cuda")
+
+    def timed(fn, reps):
+        ask.ask_enable_timing(ctx, True)
+        for _ in range(reps):
+            fn()
+        ms = sorted(ask.ask_kernel_times(ctx, cap=reps))
+        ask.ask_enable_timing(ctx, False)
+        return ms[len(ms) // 2]
+
     log("deep: %s, exhaustive" % (w,))
-    ask.ask_enable_timing(ctx, True)
-    ask.ask_dwell_exhaustive(ctx, win, out.data_ptr(), sp)
-    ex_ms = ask.ask_last_kernel_ms(ctx)
+    ex_ms = timed(lambda: ask.ask_dwell_exhaustive(ctx, win, out.data_ptr(), sp, tile=ex_tile), 1)
     ex_iters = int(out.to(torch.int64).sum().item())
     ex = out.clone()
-    res = {"workload": "mandelbrot-deep-32768x32768-D8192-width1e-6", "g": p.g, "r": p.r, "B": p.B,
-           "exhaustive": {"kernel_ms": round(ex_ms, 2), "dwell_iterations": ex_iters,
+    res = {"workload": "mandelbrot-deep-32768x32768-D8192-width1e-6", "g": g, "r": r, "B": B,
+           "tile": list(tile), "params_source": "autotuner cache" if hit else "default",
+           "exhaustive": {"kernel_ms": round(ex_ms, 2), "tile": list(ex_tile),
+                          "dwell_iterations": ex_iters,
                           "fp64_frac": round(FLOPS_PER_ITERATION * ex_iters / (ex_ms * 1e-3) / 1e12
                                              / PEAK_FP64_TFLOPS, 4)}}
     for form in ("persistent", "levels"):
         log("deep: %s" % form)
-        prm = ask.params(p.g, p.r, p.B, form)
+        prm = ask.params(g, r, B, form, 0, tile)
         st = ask.ask_dwell_subdiv(ctx, win, prm, out.data_ptr(), sp, want_stats=True)
         iters = st["iters_ring"] + st["iters_leaf"]
-        ms = []
-        for _ in range(2):
-            ask.ask_dwell_subdiv(ctx, win, prm, out.data_ptr(), sp)
-            ms.append(ask.ask_last_kernel_ms(ctx))
-        res[form] = {"kernel_ms": round(min(ms), 2), "dwell_iterations": iters,
-                     "mpix_s": round(w.pixels / (min(ms) * 1e-3) / 1e6, 1),
-                     "fp64_frac": round(FLOPS_PER_ITERATION * iters / (min(ms) * 1e-3) / 1e12
+        ms = timed(lambda: ask.ask_dwell_subdiv(ctx, win, prm, out.data_ptr(), sp), 3)
+        res[form] = {"kernel_ms": round(ms, 2), "dwell_iterations": iters,
+                     "mpix_s": round(w.pixels / (ms * 1e-3) / 1e6, 1),
+                     "fp64_frac": round(FLOPS_PER_ITERATION * iters / (ms * 1e-3) / 1e12
                                         / PEAK_FP64_TFLOPS, 4),
-                     "speedup_vs_exhaustive": round(ex_ms / min(ms), 3),
+                     "speedup_vs_exhaustive": round(ex_ms / ms, 3),
                      "pixels_differing_from_exhaustive": int((out != ex).sum().item())}
-    ask.ask_enable_timing(ctx, False)
     ask.ask_synchronize(ctx, sp)
     del out, ex
     return res
@@ -308,6 +345,7 @@ def served_leg(ctx, ask, workloads, seconds):
     log("served: %d requests over %.1f s" % (len(sched), seconds))
     res = serve.serve(ctx, sched, params_of, slots=64, log=log)
     res.pop("images")
+    res.pop("probes")
     log("served: done; sequential per-level renders of the same requests")
     # The per-level form back to back, with the serving parameters and with
     # smaller leaves (B = 32); the baseline is the faster of the two.
@@ -326,6 +364,17 @@ def served_leg(ctx, ask, workloads, seconds):
     return res
 
 
+def tuned_large(workloads, ask, autotune):
+    """(form, g, r, B, tile, exhaustive tile, source) of the main image: the
+    autotuner's cached choice for its workload class, else the defaults."""
+    p = workloads.LARGE_DEFAULT
+    hit = autotune.lookup(autotune.workload_key(ask.window(workloads.LARGE), "persistent"))
+    if hit and "tile" in hit:
+        return ("persistent", hit["g"], hit["r"], hit["B"], tuple(hit["tile"]),
+                tuple(hit["exhaustive_tile"]), "autotuner cache")
+    return (workloads.LARGE_DEFAULT_FORM, p.g, p.r, p.B, (0, 0), (16, 4), "default")
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -334,15 +383,16 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2206_02255_amd import ask
+    from paper_2206_02255_amd import ask, autotune
     import workloads
 
     w = workloads.LARGE
-    p = workloads.LARGE_DEFAULT
-    form = args.form or workloads.LARGE_DEFAULT_FORM
-    g, r, B = args.g or p.g, args.r or p.r, args.B or p.B
+    form, g, r, B, tile, ex_tile, source = tuned_large(workloads, ask, autotune)
+    if args.form or args.g or args.r or args.B:
+        form, g, r, B = args.form or form, args.g or g, args.r or r, args.B or B
+        source = "command line"
     win = ask.window(w)
-    prm = ask.params(g, r, B, form)
+    prm = ask.params(g, r, B, form, 0, tile)
     pixels = w.W * w.H
 
     if args.copy_calibration:
@@ -365,44 +415,49 @@ def main():
     st = ask.ask_dwell_subdiv(ctx, win, prm, out.data_ptr(), sp, want_stats=True)
     iters = st["iters_ring"] + st["iters_leaf"]
 
-    log("main: %s, form %s, (g, r, B) = (%d, %d, %d)" % (w, form, g, r, B))
+    log("main: %s, form %s, (g, r, B) = (%d, %d, %d), tile %s (%s)"
+        % (w, form, g, r, B, tile, source))
     for _ in range(args.warmup):
         render()
     ask.ask_synchronize(ctx, sp)
+    # The timed steps: the library records HIP events around the dominant
+    # kernel of every render on its stream, and torch events between the
+    # steps give each step's span on the same stream.
+    ask.ask_enable_timing(ctx, True)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    marks[0].record(stream)
+    for k in range(args.steps):
         render()
+        marks[k + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    kms = sorted(ask.ask_kernel_times(ctx, cap=args.steps))
+    ask.ask_enable_timing(ctx, False)
     ask.ask_synchronize(ctx, sp)
     ms_step = 1e3 * wall / args.steps
-
-    # Device time of the dominant kernel, per launch.
-    ask.ask_enable_timing(ctx, True)
-    kms = []
-    for _ in range(args.steps):
-        render()
-        kms.append(ask.ask_last_kernel_ms(ctx))
-    kernel_ms = sum(kms) / len(kms)
-    achieved = FLOPS_PER_ITERATION * iters / (kernel_ms * 1e-3) / 1e12
+    step_ms = sorted(marks[k].elapsed_time(marks[k + 1]) for k in range(args.steps))
+    kernel_ms = kms[len(kms) // 2]
+    step_median = step_ms[len(step_ms) // 2]
 
     # The same image by the exhaustive kernel and by the per-level form.
     def timed(fn, reps):
         fn()
-        ms = []
+        ask.ask_enable_timing(ctx, True)
         for _ in range(reps):
             fn()
-            ms.append(ask.ask_last_kernel_ms(ctx))
-        return min(ms)
+        ms = sorted(ask.ask_kernel_times(ctx, cap=reps))
+        ask.ask_enable_timing(ctx, False)
+        return ms[len(ms) // 2]
 
     gpu_img = out.clone()
-    ex_ms = timed(lambda: ask.ask_dwell_exhaustive(ctx, win, out.data_ptr(), sp), 2)
+    ex_ms = timed(lambda: ask.ask_dwell_exhaustive(ctx, win, out.data_ptr(), sp, tile=ex_tile), 3)
     ex_iters = int(out.to(torch.int64).sum().item())
-    lv_prm = ask.params(g, r, B, "levels")
+    mismatch = int((out != gpu_img).sum().item())
+    lv_prm = ask.params(g, r, B, "levels", 0, tile)
     lv_ms = timed(lambda: render(lv_prm), 5)
     same_forms = bool(torch.equal(out, gpu_img))
-    ask.ask_enable_timing(ctx, False)
     ask.ask_synchronize(ctx, sp)
 
     result = {
@@ -420,20 +475,26 @@ def main():
         "data": "synthetic",
         "config": {"workload": "mandelbrot-dwell-16384x16384-D2048",
                    "window": [w.x0, w.x1, w.y0, w.y1], "W": w.W, "H": w.H, "D": w.D,
-                   "form": form, "g": g, "r": r, "B": B},
+                   "form": form, "g": g, "r": r, "B": B, "tile": list(tile),
+                   "params_source": source},
         "roofline": {"bound": "alu", "kernel": "persistent_kernel" if form == "persistent"
-                     else "level_kernel", "achieved": round(achieved, 2),
+                     else "level_kernel",
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                     "traffic": measured_traffic() if (form, g, r, B) == ("persistent", 64, 4, 16)
-                     else None,
-                     "kernel_ms": round(kernel_ms, 4), "dwell_iterations": iters},
+                     "traffic": profiled("traffic_bytes_per_launch")
+                     if (form, g, r, B, tile) == ("persistent", 64, 4, 16, (0, 0)) else None,
+                     "fp64_wave_instructions": profiled("fp64_wave_instructions_per_launch")
+                     if (form, g, r, B, tile) == ("persistent", 64, 4, 16, (0, 0)) else None,
+                     "kernel_ms": round(kernel_ms, 4),
+                     "kernel_ms_timed_steps": [round(x, 4) for x in kms],
+                     "step_ms_median": round(step_median, 4),
+                     "iterations_executed": iters},
+        "mismatch_vs_exhaustive": mismatch,
         "forms": {
             "subdivision": {"form": form, "ms": round(ms_step, 4),
                             "mpix_s": round(pixels / (ms_step * 1e-3) / 1e6, 1)},
             "levels": {"kernel_ms": round(lv_ms, 4),
                        "mpix_s": round(pixels / (lv_ms * 1e-3) / 1e6, 1)},
-            "exhaustive": {"kernel_ms": round(ex_ms, 4),
+            "exhaustive": {"kernel_ms": round(ex_ms, 4), "tile": list(ex_tile),
                            "mpix_s": round(pixels / (ex_ms * 1e-3) / 1e6, 1),
                            "dwell_iterations": ex_iters,
                            "fp64_frac": round(FLOPS_PER_ITERATION * ex_iters / (ex_ms * 1e-3)
@@ -445,14 +506,21 @@ def main():
         "cpu_baseline": None,
     }
 
+    def roofline(i_count, which):
+        ach = FLOPS_PER_ITERATION * i_count / (kernel_ms * 1e-3) / 1e12
+        result["roofline"].update({"achieved": round(ach, 2), "frac": round(ach / PEAK_FP64_TFLOPS, 4),
+                                   "iterations_counted": which, "iterations": i_count})
+
+    # Until the oracle's algorithmic count is known, the kernel's own count.
+    roofline(iters, "executed by the kernel")
     log("main: done (%.3f ms per step)" % ms_step)
     if args.batch_count > 0:
-        result["forms"]["batched"] = batched_leg(ctx, torch, ask, workloads, sp, args.batch_count,
-                                                 args.batch_steps)
+        result["forms"]["batched"] = batched_leg(ctx, torch, ask, autotune, workloads, sp,
+                                                 args.batch_count, args.batch_steps)
     if args.serve_seconds > 0:
         result["forms"]["served"] = served_leg(ctx, ask, workloads, args.serve_seconds)
     if not args.no_deep:
-        result["forms"]["deep"] = deep_leg(ctx, torch, ask, workloads, sp)
+        result["forms"]["deep"] = deep_leg(ctx, torch, ask, autotune, workloads, sp)
     if not args.no_julia:
         result["forms"]["julia"] = julia_leg(ctx, torch, ask, workloads, sp, args.steps)
     if not args.no_volume:
@@ -464,7 +532,7 @@ def main():
         log("cpu baseline: the oracle on the full image")
         threads = os.cpu_count() or 1
         t0 = time.perf_counter()
-        ref_img, _ = askref.subdiv(w, g, r, B, threads=threads)
+        ref_img, ref_st = askref.subdiv(w, g, r, B, threads=threads)
         cpu_s = time.perf_counter() - t0
         gpu_np = gpu_img.cpu().numpy().view(np.uint32).reshape(w.H, w.W)
         result["cpu_baseline"] = {
@@ -473,6 +541,11 @@ def main():
             "sample": "the full 16384x16384 image, same window, D and (g, r, B)",
             "seconds": round(cpu_s, 2)}
         result["bit_exact_vs_oracle"] = bool(np.array_equal(gpu_np, ref_img))
+        # The method's algorithmic work (every scanned ring's dwells and every
+        # leaf's), from the oracle: the roofline counts it.
+        roofline(int(ref_st["iters_alg"]), "algorithmic (oracle)")
+        result["roofline"]["frac_executed"] = round(
+            FLOPS_PER_ITERATION * iters / (kernel_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)
 
     ask.ask_destroy(ctx)
     print(json.dumps(result), flush=True)

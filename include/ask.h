@@ -89,13 +89,15 @@ typedef enum ask_form {
     ASK_FORM_PERSISTENT = 2
 } ask_form;
 
-/* Leaf work in the persistent form (and in serving): how many waves share
- * one region's per-pixel work (Sec. 4.3, one block per region, SBR, against
- * several blocks per region, MBR). A leaf of more than `band` pixels is
- * queued as row bands of about `band` pixels that any wave may take (MBR);
- * smaller leaves, and every leaf with ASK_BAND_NONE, are computed whole by
- * the wave that decided them (SBR). 0 selects ASK_BAND_DEFAULT. The
- * per-level forms always compute leaves whole. */
+/* Leaf work (Sec. 4.3: one block per region, SBR, against several blocks
+ * per region, MBR): a leaf of more than `band` pixels is cut into row bands
+ * of about `band` pixels that any wave may take (MBR): in the persistent
+ * form and in serving they are queued, in the per-level forms put into the
+ * next level's table (one more level kernel takes the bands of last-level
+ * leaves). Smaller leaves, and every leaf with ASK_BAND_NONE, are computed
+ * whole by the wave that decided them (SBR); the one exception is a leaf of
+ * 65536 x 65536 pixels, whose 2^32 pixels one 32-bit stream cannot index:
+ * it is always cut into bands of 2^24 pixels. 0 selects ASK_BAND_DEFAULT. */
 #define ASK_BAND_DEFAULT 1024u
 #define ASK_BAND_NONE 0xffffffffu
 
@@ -103,11 +105,22 @@ typedef enum ask_form {
  * regions, r x r splits, stop size B (a region with both sides <= B whose
  * border is not uniform is computed per pixel). Valid: 1 <= g <= min(W, H),
  * 2 <= r <= 1024, 1 <= B <= 65536. form: an ask_form. band: 0,
- * ASK_BAND_NONE, or 64 <= band <= 2^24 (see above). */
+ * ASK_BAND_NONE, or 64 <= band <= 2^24 (see above).
+ *
+ * tile_w x tile_h: the pixel tile of one 64-lane wave, the block shape of
+ * the paper's block-size study (Sec. 6.2, its Table 2). Either both 0 (the
+ * defaults) or tile_w in {4, 8, 16, 32, 64} with tile_w * tile_h = 64.
+ *   - ask_dwell_exhaustive: each wave computes one tile, a workgroup four
+ *     tiles stacked vertically (default 16 x 4, i.e. 16 x 16 workgroups);
+ *   - subdivision: the pixels of a leaf (or leaf band) are handed to the
+ *     lanes tile by tile, tiles in row-major order over the leaf and pixels
+ *     row-major within a tile (default: the leaf's rows, one after another).
+ * The tile changes only the order of work, never an image. */
 typedef struct ask_params {
     uint32_t g, r, B;
     uint32_t form;
     uint32_t band;
+    uint32_t tile_w, tile_h;
 } ask_params;
 
 /* Work counters of a render, filled when the caller asks for them. */
@@ -118,8 +131,16 @@ typedef struct ask_stats {
     uint64_t fills[ASK_MAX_LEVELS];        /* uniform border -> filled */
     uint64_t splits[ASK_MAX_LEVELS];       /* split into children */
     uint64_t leaves[ASK_MAX_LEVELS];       /* computed per pixel */
-    uint64_t iters_ring;                   /* sum of dwells computed on borders */
-    uint64_t iters_leaf;                   /* sum of dwells computed in leaves */
+    uint64_t iters_ring;                   /* dwell iterations computed on borders (a
+                                              border found mixed stops early, so this
+                                              can be below the sum of its dwells) */
+    uint64_t iters_leaf;                   /* dwell iterations computed for leaf pixels
+                                              that are not on the leaf's border (a leaf
+                                              keeps its border's dwells), and for every
+                                              pixel of leaves cut into bands */
+    uint64_t ring_px;                      /* border pixels of scanned regions */
+    uint64_t leaf_px;                      /* pixels of leaf regions */
+    uint64_t fill_px;                      /* pixels of filled regions */
 } ask_stats;
 
 typedef struct ask_ctx ask_ctx;
@@ -131,8 +152,13 @@ const char *ask_status_str(ask_status s);
 const char *ask_last_error(const ask_ctx *ctx);
 
 /* Create a context on HIP device `device`. *out receives the context, or
- * NULL on error. Returns ASK_EDEVICE when no such device exists. */
-ask_status ask_create(ask_ctx **out, int device);
+ * NULL on error. Returns ASK_EDEVICE when no such device exists.
+ * queue_bytes: device memory to set aside now for each region queue of the
+ * context (the persistent queue and the two per-level tables), so that
+ * renders whose worst case fits allocate nothing; 0 allocates on first use.
+ * A render whose worst case exceeds a queue grows it (waiting for earlier
+ * renders on the context first). ASK_ENOMEM if it cannot be allocated. */
+ask_status ask_create(ask_ctx **out, int device, size_t queue_bytes);
 
 /* Release a context and all device memory it owns (after waiting for its
  * work). NULL is accepted. */
@@ -152,9 +178,11 @@ ask_status ask_level_count(const ask_window *win, const ask_params *params,
                            uint32_t *levels);
 
 /* Exhaustive image (Sec. 4.1): d_out[py*W + px] = dwell(c(px, py)) for all
- * pixels. d_out: device memory, W*H uint32, caller-owned. */
+ * pixels. d_out: device memory, W*H uint32, caller-owned. params: NULL, or
+ * parameters of which only the wave tile (tile_w, tile_h) is read and
+ * checked; the other fields are ignored. */
 ask_status ask_dwell_exhaustive(ask_ctx *ctx, const ask_window *win,
-                                uint32_t *d_out, void *stream);
+                                const ask_params *params, uint32_t *d_out, void *stream);
 
 /* Subdivision image (Sec. 4.2.1, 5): every region of the initial g x g grid
  * has its border dwells computed; a uniform border fills the region with
@@ -204,7 +232,8 @@ ask_status ask_dwell_batch(ask_ctx *ctx, uint32_t n, const ask_window *wins,
 ask_status ask_synchronize(ask_ctx *ctx, void *stream);
 
 /* Record HIP events, on the render's stream, around the dominant kernels of
- * later renders on this context (on != 0), or stop (on == 0). Dominant
+ * later renders on this context (on != 0; the count of timed renders starts
+ * again from 0), or stop (on == 0). Dominant
  * kernels: the exhaustive kernel; the level kernels, from the first one's
  * start to the last one's end; the persistent kernel. Set-up kernels (counter
  * reset, level-0 seeding) are outside the events. */
@@ -213,6 +242,11 @@ ask_status ask_enable_timing(ask_ctx *ctx, int on);
 /* Device time, in milliseconds, of the dominant kernels of the last render
  * timed on this context. Waits for that render; ASK_EINVAL if there is none. */
 ask_status ask_last_kernel_ms(ask_ctx *ctx, float *ms);
+
+/* Device times, in milliseconds, of the dominant kernels of the last
+ * min(timed renders, cap, 256) renders timed since ask_enable_timing(ctx, 1),
+ * oldest first, into ms[0 .. *n). Waits for those renders. */
+ask_status ask_kernel_times(ask_ctx *ctx, float *ms, uint32_t cap, uint32_t *n);
 
 /* Longest time, in seconds (0 to 3600, default 10), that one wave of the
  * persistent kernel waits for a region before it records ASK_ETIMEOUT and
@@ -278,8 +312,11 @@ ask_status ask_server_reap(ask_server *sv, uint64_t *tickets, int32_t *status,
 
 /* *done = 1 when request `ticket` has finished (reaping it if needed), else
  * 0. Returns the request's status once finished; ASK_EINVAL for a ticket
- * never issued. Does not wait. */
-ask_status ask_server_poll(ask_server *sv, uint64_t ticket, int *done);
+ * never issued. latency_s (may be NULL) receives, once finished, the
+ * request's latency in seconds: from its ask_server_submit to the host's
+ * first sight of its completion (by a reap or a poll), on the host's
+ * monotonic clock; -1 while it runs. Does not wait. */
+ask_status ask_server_poll(ask_server *sv, uint64_t ticket, int *done, double *latency_s);
 
 /* Requests posted and not yet reaped. */
 ask_status ask_server_in_flight(const ask_server *sv, uint32_t *n);

@@ -37,7 +37,7 @@ class ask_window(C.Structure):
 
 class ask_params(C.Structure):
     _fields_ = [("g", C.c_uint32), ("r", C.c_uint32), ("B", C.c_uint32), ("form", C.c_uint32),
-                ("band", C.c_uint32)]
+                ("band", C.c_uint32), ("tile_w", C.c_uint32), ("tile_h", C.c_uint32)]
 
 
 class ask_server_cfg(C.Structure):
@@ -48,12 +48,14 @@ class ask_stats(C.Structure):
     _fields_ = [("levels", C.c_uint32), ("overflow", C.c_uint32),
                 ("regions", C.c_uint64 * MAX_LEVELS), ("fills", C.c_uint64 * MAX_LEVELS),
                 ("splits", C.c_uint64 * MAX_LEVELS), ("leaves", C.c_uint64 * MAX_LEVELS),
-                ("iters_ring", C.c_uint64), ("iters_leaf", C.c_uint64)]
+                ("iters_ring", C.c_uint64), ("iters_leaf", C.c_uint64),
+                ("ring_px", C.c_uint64), ("leaf_px", C.c_uint64), ("fill_px", C.c_uint64)]
 
     def as_dict(self):
         n = self.levels
         d = {"levels": n, "overflow": self.overflow, "iters_ring": self.iters_ring,
-             "iters_leaf": self.iters_leaf}
+             "iters_leaf": self.iters_leaf, "ring_px": self.ring_px, "leaf_px": self.leaf_px,
+             "fill_px": self.fill_px}
         for k in ("regions", "fills", "splits", "leaves"):
             d[k] = list(getattr(self, k)[:n])
         return d
@@ -92,13 +94,14 @@ _P = C.c_void_p
 SIGNATURES = {
     "ask_status_str": (C.c_char_p, [C.c_int]),
     "ask_last_error": (C.c_char_p, [_P]),
-    "ask_create": (C.c_int, [C.POINTER(_P), C.c_int]),
+    "ask_create": (C.c_int, [C.POINTER(_P), C.c_int, C.c_size_t]),
     "ask_destroy": (C.c_int, [_P]),
     "ask_validate": (C.c_int, [C.POINTER(ask_window), C.POINTER(ask_params)]),
     "ask_mapping": (C.c_int, [C.POINTER(ask_window), C.POINTER(C.c_double)]),
     "ask_level_count": (C.c_int, [C.POINTER(ask_window), C.POINTER(ask_params),
                                   C.POINTER(C.c_uint32)]),
-    "ask_dwell_exhaustive": (C.c_int, [_P, C.POINTER(ask_window), _P, _P]),
+    "ask_dwell_exhaustive": (C.c_int, [_P, C.POINTER(ask_window), C.POINTER(ask_params), _P,
+                                       _P]),
     "ask_dwell_subdiv": (C.c_int, [_P, C.POINTER(ask_window), C.POINTER(ask_params), _P, _P,
                                    C.POINTER(ask_stats)]),
     "ask_dwell_batch": (C.c_int, [_P, C.c_uint32, C.POINTER(ask_window), C.POINTER(ask_params),
@@ -107,12 +110,13 @@ SIGNATURES = {
     "ask_set_wait_limit": (C.c_int, [_P, C.c_double]),
     "ask_enable_timing": (C.c_int, [_P, C.c_int]),
     "ask_last_kernel_ms": (C.c_int, [_P, C.POINTER(C.c_float)]),
+    "ask_kernel_times": (C.c_int, [_P, C.POINTER(C.c_float), C.c_uint32, C.POINTER(C.c_uint32)]),
     "ask_server_create": (C.c_int, [_P, C.POINTER(ask_server_cfg), C.POINTER(_P)]),
     "ask_server_submit": (C.c_int, [_P, C.POINTER(ask_window), C.POINTER(ask_params), _P,
                                     C.POINTER(C.c_uint64)]),
     "ask_server_reap": (C.c_int, [_P, C.POINTER(C.c_uint64), C.POINTER(C.c_int32), C.c_uint32,
                                   C.POINTER(C.c_uint32)]),
-    "ask_server_poll": (C.c_int, [_P, C.c_uint64, C.POINTER(C.c_int)]),
+    "ask_server_poll": (C.c_int, [_P, C.c_uint64, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "ask_server_in_flight": (C.c_int, [_P, C.POINTER(C.c_uint32)]),
     "ask_server_destroy": (C.c_int, [_P]),
     "ask3_validate": (C.c_int, [C.POINTER(ask_volume), C.POINTER(ask3_params)]),
@@ -161,12 +165,17 @@ def window(w):
 BAND_DEFAULT, BAND_NONE = 1024, 0xffffffff
 
 
-def params(g, r, B, form="levels", band=0):
-    """ask_params; band: pixels per queued leaf band in the persistent form and
-    in serving (0: BAND_DEFAULT; BAND_NONE: every leaf computed whole by the
-    wave that decides it)."""
+def params(g, r, B, form="levels", band=0, tile=(0, 0)):
+    """ask_params; band: pixels per leaf band (0: BAND_DEFAULT; BAND_NONE:
+    every leaf computed whole by the wave that decides it); tile: the wave's
+    pixel tile (tile_w, tile_h), (0, 0) for the defaults."""
     return ask_params(int(g), int(r), int(B), FORMS[form] if isinstance(form, str) else int(form),
-                      int(band))
+                      int(band), int(tile[0]), int(tile[1]))
+
+
+def tile_params(tile):
+    """ask_params that carry only a wave tile, for ask_dwell_exhaustive."""
+    return params(1, 2, 1, "levels", 0, tile)
 
 
 def _check(s, ctx=None):
@@ -195,9 +204,9 @@ def ask_level_count(win, prm):
     return n.value
 
 
-def ask_create(device=0):
+def ask_create(device=0, queue_bytes=0):
     h = _P()
-    _check(lib.ask_create(C.byref(h), int(device)))
+    _check(lib.ask_create(C.byref(h), int(device), int(queue_bytes)))
     return h
 
 
@@ -205,8 +214,11 @@ def ask_destroy(ctx):
     _check(lib.ask_destroy(ctx))
 
 
-def ask_dwell_exhaustive(ctx, win, d_out, stream=0):
-    _check(lib.ask_dwell_exhaustive(ctx, C.byref(win), _P(d_out), _P(stream)), ctx)
+def ask_dwell_exhaustive(ctx, win, d_out, stream=0, tile=None):
+    """tile: None (the default 16 x 4 wave tile) or (tile_w, tile_h)."""
+    prm = tile_params(tile) if tile is not None else None
+    _check(lib.ask_dwell_exhaustive(ctx, C.byref(win), C.byref(prm) if prm is not None else None,
+                                    _P(d_out), _P(stream)), ctx)
 
 
 def ask_dwell_subdiv(ctx, win, prm, d_out, stream=0, want_stats=False):
@@ -232,6 +244,15 @@ def ask_last_kernel_ms(ctx):
     ms = C.c_float()
     _check(lib.ask_last_kernel_ms(ctx, C.byref(ms)), ctx)
     return ms.value
+
+
+def ask_kernel_times(ctx, cap=256):
+    """Device times (ms) of the renders timed since ask_enable_timing, oldest
+    first (at most the last 256)."""
+    ms = (C.c_float * cap)()
+    n = C.c_uint32()
+    _check(lib.ask_kernel_times(ctx, ms, int(cap), C.byref(n)), ctx)
+    return list(ms[:n.value])
 
 
 def ask_dwell_batch(ctx, wins, prms, d_outs, stream=0, want_stats=False):
@@ -283,12 +304,13 @@ def ask_server_reap(sv, cap=256):
 
 
 def ask_server_poll(sv, ticket):
-    """(done, status) of one request."""
+    """(done, status, latency in s or None while running) of one request."""
     d = C.c_int()
-    s = lib.ask_server_poll(sv, int(ticket), C.byref(d))
+    lat = C.c_double()
+    s = lib.ask_server_poll(sv, int(ticket), C.byref(d), C.byref(lat))
     if s == EINVAL:
         _check(s, _live_servers.get(sv.value))
-    return bool(d.value), s
+    return bool(d.value), s, (lat.value if lat.value >= 0 else None)
 
 
 def ask_server_in_flight(sv):

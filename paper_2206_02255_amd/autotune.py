@@ -203,9 +203,40 @@ def model_optimum(grid, n, A, P, lam, q, c=64, scheme="sbr"):
     return tuple(int(v) for v in grid[i]), float(t[i])
 
 
+# The measured choices of the workload classes tuned so far, kept beside the
+# package so that every run of the benchmark reads the same choices.
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
+
+TILES = [(4, 16), (8, 8), (16, 4), (32, 2), (64, 1)]
+
+
 def cache_path():
-    return os.environ.get("ASK_TUNE_CACHE", os.path.join(
-        os.path.expanduser("~"), ".cache", "paper_2206_02255_amd", "tune.json"))
+    return os.environ.get("ASK_TUNE_CACHE", DEFAULT_CACHE)
+
+
+def load_cache(path=None):
+    path = path or cache_path()
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def store(key, entry, path=None):
+    """Record the measured choice of one workload class in the cache."""
+    path = path or cache_path()
+    cache = load_cache(path)
+    cache[key] = entry
+    d = os.path.dirname(path)
+    if d:
+        os.makedirs(d, exist_ok=True)
+    with open(path, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+
+
+def lookup(key, path=None):
+    """The cached choice of a workload class, or None."""
+    return load_cache(path).get(key)
 
 
 def workload_key(win, form):
@@ -213,18 +244,89 @@ def workload_key(win, form):
     return "%dx%d-D%d-w1e%d-%s" % (win.W, win.H, win.D, int(math.floor(math.log10(width))), form)
 
 
+def _median_ms(ctx, render, reps):
+    import torch
+    stream = torch.cuda.current_stream().cuda_stream
+    render()
+    ask.ask_synchronize(ctx, stream)
+    ask.ask_enable_timing(ctx, True)
+    try:
+        for _ in range(reps):
+            render()
+        ms = sorted(ask.ask_kernel_times(ctx))
+    finally:
+        ask.ask_enable_timing(ctx, False)
+        ask.ask_synchronize(ctx, stream)
+    return ms[len(ms) // 2]
+
+
+def tile_sweep(ctx, win, g, r, B, form="persistent", tiles=None, reps=5, out=None):
+    """Kernel time (median of reps) of the subdivision render of ``win`` with
+    (g, r, B) for each wave tile (the block-size study of Sec. 6.2): (0, 0),
+    the default row order of leaf pixels, then every tile of ``tiles``."""
+    import torch
+    stream = torch.cuda.current_stream().cuda_stream
+    if out is None:
+        out = torch.empty(win.W * win.H, dtype=torch.int32, device="cuda")
+    rows = []
+    for tile in [(0, 0)] + list(tiles or TILES):
+        prm = ask.params(g, r, B, form, 0, tile)
+        ms = _median_ms(ctx, lambda: ask.ask_dwell_subdiv(ctx, win, prm, out.data_ptr(), stream),
+                        reps)
+        rows.append({"tile": list(tile), "ms": ms})
+    return rows
+
+
+def exhaustive_tile_sweep(ctx, win, tiles=None, reps=3, out=None):
+    """Kernel time (median of reps) of the exhaustive image of ``win`` for each
+    wave tile."""
+    import torch
+    stream = torch.cuda.current_stream().cuda_stream
+    if out is None:
+        out = torch.empty(win.W * win.H, dtype=torch.int32, device="cuda")
+    rows = []
+    for tile in list(tiles or TILES):
+        ms = _median_ms(ctx, lambda: ask.ask_dwell_exhaustive(ctx, win, out.data_ptr(), stream,
+                                                              tile=tile), reps)
+        rows.append({"tile": list(tile), "ms": ms})
+    return rows
+
+
+def batch_rule_sweep(ctx, images, rules, reps=1):
+    """Kernel time of the batch of ``images`` (workloads.Window) in one
+    persistent launch for each per-image parameter rule of ``rules``: dicts
+    with s0 (level-0 region side: g = side // s0, clamped to [1, 256]), r, B
+    and tile. Returns the rules with their times, fastest first."""
+    import numpy as np
+    import torch
+    import workloads
+    stream = torch.cuda.current_stream().cuda_stream
+    sizes = [w.pixels for w in images]
+    offs = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    out = torch.empty(int(sum(sizes)), dtype=torch.int32, device="cuda")
+    ptrs = [out.data_ptr() + 4 * int(o) for o in offs]
+    wins = [ask.window(w) for w in images]
+    rows = []
+    for rule in rules:
+        prms = []
+        for w in images:
+            p = workloads.rule_params(w.W, rule["s0"], rule["r"], rule["B"])
+            prms.append(ask.params(p.g, p.r, p.B, "persistent", 0, rule.get("tile", (0, 0))))
+        ms = _median_ms(ctx, lambda: ask.ask_dwell_batch(ctx, wins, prms, ptrs, stream), reps)
+        rows.append(dict(rule, ms=ms))
+    del out
+    return sorted(rows, key=lambda row: row["ms"])
+
+
 def tune(ctx, win, grid=None, form="persistent", reps=3, q=256, use_cache=True):
     """Measured optimum (g, r, B) for window ``win``, from the cache when it
     holds this workload class, else from a sweep (then cached). Returns a
     dict with the measured optimum, the model optimum and the sweep rows."""
     key = workload_key(win, form)
-    path = cache_path()
-    cache = {}
-    if use_cache and os.path.exists(path):
-        with open(path) as f:
-            cache = json.load(f)
-        if key in cache:
-            return cache[key]
+    if use_cache:
+        hit = lookup(key)
+        if hit is not None and "rows" in hit:
+            return hit
     grid = grid or default_grid(min(win.W, win.H))
     rows = sweep(ctx, win, grid, form, reps)
     n = min(win.W, win.H)
@@ -239,16 +341,82 @@ def tune(ctx, win, grid=None, form="persistent", reps=3, q=256, use_cache=True):
                             "log_rms_error": err, "q": q, "c": 64},
               "rows": rows}
     if use_cache:
-        cache[key] = result
-        os.makedirs(os.path.dirname(path), exist_ok=True)
-        with open(path, "w") as f:
-            json.dump(cache, f, indent=1)
+        store(key, result)
     return result
+
+
+BATCH_KEY = "batch-256-seed4-persistent"
+
+
+def tune_class(ctx, name, log=print):
+    """Measure the choices of one workload class of the benchmark and store
+    them in the cache: ``large`` (the paper's window at 16384^2, D = 2048) and
+    ``deep`` (the deep zoom at 32768^2, D = 8192): (g, r, B), then the wave
+    tile of the subdivision's leaves and of the exhaustive kernel; ``batch``
+    (256 boundary images): the per-image rule (level-0 region side, r, B),
+    then its wave tile."""
+    import torch
+    import workloads
+    if name == "batch":
+        ims = workloads.batch_images()
+        rules = [{"s0": s0, "r": r, "B": B, "tile": [0, 0]}
+                 for s0 in (128, 256, 512) for r in (2, 4) for B in (32, 64, 128)]
+        rows = batch_rule_sweep(ctx, ims, rules)
+        for row in rows[:5]:
+            log("batch rule %s" % row)
+        best = dict(rows[0])
+        trows = batch_rule_sweep(ctx, ims, [dict(best, tile=list(t)) for t in TILES])
+        for row in trows:
+            log("batch tile %s" % row)
+        if trows[0]["ms"] < best["ms"]:
+            best = dict(trows[0])
+        entry = {"rule": {k: best[k] for k in ("s0", "r", "B", "tile")}, "ms": best["ms"],
+                 "rows": rows, "tile_rows": trows}
+        store(BATCH_KEY, entry)
+        return BATCH_KEY, entry
+    if name == "large":
+        w, reps = workloads.LARGE, 5
+        grid = [(g, r, B) for g in (16, 32, 64, 128) for r in (2, 4) for B in (16, 32, 64)]
+    elif name == "deep":
+        w, reps = workloads.deep_window(), 1
+        grid = [(g, r, B) for g in (32, 64, 128) for r in (2, 4) for B in (32, 64, 128)]
+    else:
+        raise ValueError(name)
+    win = ask.window(w)
+    out = torch.empty(w.W * w.H, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    rows = []
+    for g, r, B in grid:
+        prm = ask.params(g, r, B, "persistent")
+        ms = _median_ms(ctx, lambda: ask.ask_dwell_subdiv(ctx, win, prm, out.data_ptr(), stream),
+                        reps)
+        rows.append({"g": g, "r": r, "B": B, "ms": ms})
+        log("%s g=%d r=%d B=%d %.3f ms" % (name, g, r, B, ms))
+    rows.sort(key=lambda row: row["ms"])
+    best = rows[0]
+    trows = tile_sweep(ctx, win, best["g"], best["r"], best["B"], "persistent", reps=reps, out=out)
+    for row in trows:
+        log("%s leaf tile %s %.3f ms" % (name, row["tile"], row["ms"]))
+    tbest = min(trows, key=lambda row: row["ms"])
+    erows = exhaustive_tile_sweep(ctx, win, reps=max(1, min(3, reps)), out=out)
+    for row in erows:
+        log("%s exhaustive tile %s %.3f ms" % (name, row["tile"], row["ms"]))
+    ebest = min(erows, key=lambda row: row["ms"])
+    key = workload_key(win, "persistent")
+    entry = {"g": best["g"], "r": best["r"], "B": best["B"], "tile": tbest["tile"],
+             "ms": tbest["ms"], "exhaustive_tile": ebest["tile"], "exhaustive_ms": ebest["ms"],
+             "rows": rows, "tile_rows": trows, "exhaustive_tile_rows": erows}
+    store(key, entry)
+    del out
+    return key, entry
 
 
 def main(argv=None):
     import torch
     ap = argparse.ArgumentParser(description="(g, r, B) sweep on the paper's window")
+    ap.add_argument("--tune", default=None, nargs="+", choices=["large", "deep", "batch"],
+                    help="measure the benchmark's workload classes and store their choices in "
+                         "the cache (ASK_TUNE_CACHE, default tuned.json beside the package)")
     ap.add_argument("--size", type=int, default=16384)
     ap.add_argument("--dwell", type=int, default=2048)
     ap.add_argument("--form", default="persistent", choices=["levels", "persistent"])
@@ -266,6 +434,16 @@ def main(argv=None):
     args = ap.parse_args(argv)
     import workloads
     from workloads import LARGE_SWEEP, paper_window
+    if args.tune:
+        ctx = ask.ask_create(0)
+        try:
+            for name in args.tune:
+                key, entry = tune_class(ctx, name, log=lambda m: print(m, flush=True))
+                print(json.dumps({key: {k: v for k, v in entry.items() if not k.endswith("rows")}}),
+                      flush=True)
+        finally:
+            ask.ask_destroy(ctx)
+        return
     w = {"paper": lambda: paper_window(args.size, args.dwell), "deep": workloads.deep_window,
          "julia": lambda: workloads.JULIA}[args.window]()
     if args.schemes:

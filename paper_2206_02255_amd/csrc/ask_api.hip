@@ -36,14 +36,13 @@ struct ask_ctx {
     double clock_hz = 1e8;                // rate of the device's constant clock
     bool timing = false;                  // record events around the dominant kernels
     bool timed = false;                   // the events hold a render
-    hipEvent_t ev[2] = {nullptr, nullptr};
-    // Batches: image table and level-0 seed offsets on the device, staged
-    // through pinned host memory whose last copy `staged` marks.
+    // Start and end events of the last kTimingRing timed renders; render k
+    // (counting from the last ask_enable_timing) uses pair k % kTimingRing.
+    std::vector<hipEvent_t> ev;
+    uint64_t timed_count = 0;
+    // Batches: image table and level-0 seed offsets on the device.
     void *table = nullptr;
     size_t table_bytes = 0;
-    void *staging = nullptr;
-    size_t staging_bytes = 0;
-    hipEvent_t staged = nullptr;
     // Completion of the last render or exhaustive image enqueued on this
     // context (any stream): buffers are reallocated only after it.
     hipEvent_t last = nullptr;
@@ -58,6 +57,8 @@ struct ask_ctx {
 };
 
 namespace {
+
+constexpr uint32_t kTimingRing = 256;
 
 // Entries per queue buffer never exceed this (1 GiB of 16-byte entries); a
 // render whose worst case needs more is checked for overflow after it runs.
@@ -109,8 +110,19 @@ ask_status check_window(const ask_window *w) {
     return ASK_OK;
 }
 
+// The wave tile: both 0 (defaults), or a power-of-two width of 4 to 64
+// pixels whose tile holds exactly one wave's 64 lanes.
+bool check_tile(const ask_params *p) {
+    if (p->tile_w == 0 && p->tile_h == 0)
+        return true;
+    const uint32_t tw = p->tile_w;
+    return tw >= 4 && tw <= 64 && (tw & (tw - 1)) == 0 && p->tile_h * tw == 64;
+}
+
 ask_status check_params(const ask_window *w, const ask_params *p) {
     if (!p)
+        return ASK_EINVAL;
+    if (!check_tile(p))
         return ASK_EINVAL;
     if (p->g < 1 || p->g > w->W || p->g > w->H)
         return ASK_EINVAL;
@@ -195,6 +207,12 @@ Image make_image(const ask_window *w, const ask_params *p, uint32_t *out) {
     im.r = p ? p->r : 2;
     im.B = p ? p->B : 1;
     im.band = p && p->band ? p->band : kLeafTask;
+    // Only a 65536 x 65536 leaf has more pixels than one 32-bit stream can
+    // index: even without bands it is cut into bands of 2^24 pixels.
+    if ((uint64_t)im.W * im.H > im.band && im.band > (1u << 24))
+        im.band = 1u << 24;
+    im.tile_w = p ? p->tile_w : 0;
+    im.tile_h = p ? p->tile_h : 0;
     im.julia = w->set == ASK_SET_JULIA ? 1u : 0u;
     im.jr = im.julia ? w->cr : 0.0;
     im.ji = im.julia ? w->ci : 0.0;
@@ -290,6 +308,9 @@ ask_status read_stats(ask_ctx *ctx, hipStream_t s, ask_stats *out) {
         }
         out->iters_ring = ds.iters_ring;
         out->iters_leaf = ds.iters_leaf;
+        out->ring_px = ds.ring_px;
+        out->leaf_px = ds.leaf_px;
+        out->fill_px = ds.fill_px;
     }
     return st;
 }
@@ -301,9 +322,13 @@ hipError_t mark(ask_ctx *ctx, int which, hipStream_t s) {
     if (hipStreamIsCapturing(s, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone)
         return hipSuccess;  // a graph is not timed by the context's events
     (void)hipGetLastError();
-    if (which == 1)
+    const size_t slot = ctx->timed_count % kTimingRing;
+    const hipError_t e = hipEventRecord(ctx->ev[2 * slot + which], s);
+    if (which == 1 && e == hipSuccess) {
         ctx->timed = true;
-    return hipEventRecord(ctx->ev[which], s);
+        ++ctx->timed_count;
+    }
+    return e;
 }
 
 }  // namespace
@@ -348,7 +373,7 @@ ask_status ask_level_count(const ask_window *win, const ask_params *params, uint
     return ASK_OK;
 }
 
-ask_status ask_create(ask_ctx **out, int device) {
+ask_status ask_create(ask_ctx **out, int device, size_t queue_bytes) {
     if (!out)
         return ASK_EINVAL;
     *out = nullptr;
@@ -371,12 +396,6 @@ ask_status ask_create(ask_ctx **out, int device) {
     if (e == hipSuccess)
         e = hipMemset(ctx->ctrl, 0, kCtrlWords * sizeof(uint32_t));
     if (e == hipSuccess)
-        e = hipEventCreate(&ctx->ev[0]);
-    if (e == hipSuccess)
-        e = hipEventCreate(&ctx->ev[1]);
-    if (e == hipSuccess)
-        e = hipEventCreateWithFlags(&ctx->staged, hipEventDisableTiming);
-    if (e == hipSuccess)
         e = hipEventCreateWithFlags(&ctx->last, hipEventDisableTiming);
     if (e == hipSuccess)
         e = occupancy_level(&ctx->occ_level);
@@ -395,6 +414,20 @@ ask_status ask_create(ask_ctx **out, int device) {
     ctx->cus = prop.multiProcessorCount;
     ctx->occ_level = std::max(1, ctx->occ_level);
     ctx->occ_persistent = std::max(1, ctx->occ_persistent);
+    if (queue_bytes) {
+        const size_t entries = std::max<size_t>(1, queue_bytes / sizeof(Region));
+        size_t cap0 = 0, cap1 = 0;
+        ask_status st = grow(ctx, &ctx->queue, &ctx->queue_cap, entries, true);
+        if (st == ASK_OK)
+            st = grow(ctx, &ctx->lvq[0], &cap0, entries, false);
+        if (st == ASK_OK)
+            st = grow(ctx, &ctx->lvq[1], &cap1, entries, false);
+        ctx->lvq_cap = std::min(cap0, cap1);
+        if (st != ASK_OK) {
+            ask_destroy(ctx);
+            return st;
+        }
+    }
     *out = ctx;
     return ASK_OK;
 }
@@ -412,31 +445,28 @@ ask_status ask_destroy(ask_ctx *ctx) {
         (void)hipFree(ctx->lvq[0]);
         (void)hipFree(ctx->lvq[1]);
         (void)hipFree(ctx->queue);
-        if (ctx->ev[0])
-            (void)hipEventDestroy(ctx->ev[0]);
-        if (ctx->ev[1])
-            (void)hipEventDestroy(ctx->ev[1]);
-        if (ctx->staged)
-            (void)hipEventDestroy(ctx->staged);
+        for (hipEvent_t ev : ctx->ev)
+            (void)hipEventDestroy(ev);
         if (ctx->last)
             (void)hipEventDestroy(ctx->last);
         for (void *p : ctx->retired)
             (void)hipFree(p);
         (void)hipFree(ctx->table);
-        (void)hipHostFree(ctx->staging);
     }
     delete ctx;
     return ASK_OK;
 }
 
-ask_status ask_dwell_exhaustive(ask_ctx *ctx, const ask_window *win, uint32_t *d_out,
-                                void *stream) {
+ask_status ask_dwell_exhaustive(ask_ctx *ctx, const ask_window *win, const ask_params *params,
+                                uint32_t *d_out, void *stream) {
     if (!ctx)
         return ASK_EINVAL;
-    if (check_window(win) != ASK_OK || !d_out)
-        return fail(ctx, ASK_EINVAL, "invalid window or output%s", nullptr);
+    if (check_window(win) != ASK_OK || !d_out || (params && !check_tile(params)))
+        return fail(ctx, ASK_EINVAL, "invalid window, wave tile or output%s", nullptr);
     DeviceGuard guard(ctx->device);
-    const Image im = make_image(win, nullptr, d_out);
+    Image im = make_image(win, nullptr, d_out);
+    im.tile_w = params ? params->tile_w : 0;
+    im.tile_h = params ? params->tile_h : 0;
     hipError_t e = mark(ctx, 0, (hipStream_t)stream);
     if (e == hipSuccess)
         e = launch_exhaustive(im, (hipStream_t)stream);
@@ -453,14 +483,158 @@ ask_status ask_dwell_exhaustive(ask_ctx *ctx, const ask_window *win, uint32_t *d
 
 namespace {
 
-// Render n images (n >= 1) that share one form in one sequence of launches:
-// counters reset, level-0 seeding of every image, then the level kernels or
-// the persistent kernel over one queue. `ims` holds each image's constants.
+// What a render of n images in one form needs, worked out on the host from
+// the images alone: level count, level-0 seeds and worst-case queue sizes.
+struct Plan {
+    uint32_t levels = 0;
+    uint64_t nseeds = 0;
+    Bounds b;
+    bool banded = false;      // some image cuts leaves into bands
+    uint64_t band_bound = 0;  // per-level form: bands one level's table may hold
+    uint64_t need = 0;        // entries: the persistent queue, or each per-level table
+};
+
+ask_status plan_render(ask_ctx *ctx, const Image *ims, uint32_t n, uint32_t form, Plan &p) {
+    for (uint32_t i = 0; i < n; ++i) {
+        const Image &im = ims[i];
+        const uint32_t lv_i = add_bounds(im, p.b);
+        if (lv_i > (uint32_t)kMaxLevels - 1)
+            return fail(ctx, ASK_EINVAL, "too many levels%s", nullptr);
+        p.levels = std::max(p.levels, lv_i);
+        p.nseeds += (uint64_t)im.g * im.g;
+    }
+    if (p.nseeds > 0x7fffffffull)
+        return fail(ctx, ASK_EINVAL, "too many level-0 regions%s", nullptr);
+    uint64_t widest = 0;
+    for (uint32_t lv = 0; lv < p.levels; ++lv)
+        widest = std::max(widest, p.b.level[lv]);
+    // Per-level form: a level's table holds its regions and the bands of the
+    // leaves decided one level up, at most pixels / (band / 2) plus one per
+    // leaf; bands of last-level leaves take one more level kernel.
+    p.banded = p.b.band != ASK_BAND_NONE;
+    p.band_bound = p.banded ? p.b.pixels / (p.b.band / 2) + widest : 0;
+    p.need = form == ASK_FORM_PERSISTENT ? p.b.queue_entries() : widest + p.band_bound;
+    return ASK_OK;
+}
+
+// Device memory a render runs in, and how it is launched.
+struct Buffers {
+    uint32_t *ctrl = nullptr;
+    DevStats *stats = nullptr;            // nullptr: no counters
+    Region *lvq[2] = {nullptr, nullptr};  // per-level tables
+    Region *queue = nullptr;              // persistent queue
+    uint64_t cap = 0;                     // entries of the queue, or of each table
+    const Image *table = nullptr;         // device image table (n > 1), or nullptr
+    const uint32_t *seed_base = nullptr;  // its n + 1 seed offsets
+    uint32_t epoch = 1;                   // tag of this launch's queue entries
+    bool clear_queue = false;             // clear the queue's first `cap` entries first
+    uint64_t wait_ticks = 0;
+    uint32_t grid_persistent = 1;         // workgroups of the persistent kernel
+    uint32_t resident_level = 1;          // workgroups the per-level kernels keep resident
+};
+
+// Write `words` (n 32-bit words) to device memory at dst with kernels that
+// carry the data in their arguments: a stream capture records them as
+// kernel nodes, so a graph replays the data itself and depends on no host
+// buffer.
+hipError_t upload_words(uint32_t *dst, const uint32_t *words, size_t n, hipStream_t s) {
+    for (size_t off = 0; off < n; off += kWordsPerWrite) {
+        WordsArg w{};
+        w.dst = dst + off;
+        w.n = (uint32_t)std::min<size_t>(kWordsPerWrite, n - off);
+        memcpy(w.words, words + off, w.n * sizeof(uint32_t));
+        const hipError_t e = launch_write_words(w, s);
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+// The launch sequence of a render: counters reset, level-0 seeding of every
+// image, then the persistent kernel over one queue or one kernel per level.
+// ctx (may be nullptr) records the timing events and read-back errors.
+ask_status launch_render(ask_ctx *ctx, const Plan &p, const Buffers &bf, const Image *ims,
+                         uint32_t n, uint32_t form, hipStream_t s) {
+    SubdivArgs a{};
+    a.nimg = n;
+    a.ctrl = bf.ctrl;
+    a.stats = bf.stats;
+    if (n == 1)
+        a.single = ims[0];
+    a.table = n == 1 ? nullptr : bf.table;
+    a.seed_base = bf.seed_base;
+    const uint32_t cap = (uint32_t)std::min<uint64_t>(bf.cap, 0xffffffffu - 65536u);
+    hipError_t e = launch_reset(bf.ctrl, bf.stats, s);
+    if (e != hipSuccess)
+        return hip_fail(ctx, e, "reset kernel launch");
+    if (form == ASK_FORM_PERSISTENT) {
+        if (bf.clear_queue) {
+            e = launch_clear_queue(bf.queue, cap, s);
+            if (e != hipSuccess)
+                return hip_fail(ctx, e, "queue clear launch");
+        }
+        a.queue = bf.queue;
+        a.cap = cap;
+        a.epoch = bf.epoch;
+        a.wait_ticks = bf.wait_ticks;
+        e = launch_seed_queue(a, (uint32_t)p.nseeds, s);
+        if (e == hipSuccess && ctx)
+            e = mark(ctx, 0, s);
+        if (e == hipSuccess)
+            e = launch_persistent(a, bf.grid_persistent, s);
+        if (e == hipSuccess && ctx)
+            e = mark(ctx, 1, s);
+        if (e != hipSuccess)
+            return hip_fail(ctx, e, "persistent launch");
+        return ASK_OK;
+    }
+    a.cap = cap;
+    a.epoch = 0;
+    a.out = bf.lvq[0];
+    e = launch_seed_levels(a, (uint32_t)p.nseeds, s);
+    if (e == hipSuccess && ctx)
+        e = mark(ctx, 0, s);
+    if (e != hipSuccess)
+        return hip_fail(ctx, e, "seed kernel launch");
+    for (uint32_t lv = 0; lv < p.levels + (p.banded ? 1u : 0u); ++lv) {
+        a.level = lv;
+        a.in = bf.lvq[lv & 1];
+        a.out = bf.lvq[(lv + 1) & 1];
+        if (form == ASK_FORM_LEVELS_READBACK) {
+            uint32_t cnt = 0;
+            e = hipMemcpyAsync(&cnt, bf.ctrl + kCount + lv, sizeof(cnt), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess)
+                e = hipStreamSynchronize(s);
+            if (e != hipSuccess)
+                return hip_fail(ctx, e, "level count readback");
+            cnt = std::min<uint32_t>(cnt, a.cap);
+            if (cnt == 0)
+                break;
+            e = launch_level_exact(a, cnt, s);
+        } else {
+            const uint64_t entries = p.b.level[lv] + (lv > 0 ? p.band_bound : 0);
+            const uint64_t blocks =
+                std::min<uint64_t>(bf.resident_level, (entries + kWavesPerBlock - 1) / kWavesPerBlock);
+            e = launch_level(a, (uint32_t)std::max<uint64_t>(1, blocks), s);
+        }
+        if (e != hipSuccess)
+            return hip_fail(ctx, e, "level kernel launch");
+    }
+    if (ctx) {
+        e = mark(ctx, 1, s);
+        if (e != hipSuccess)
+            return hip_fail(ctx, e, "hipEventRecord");
+    }
+    return ASK_OK;
+}
+
+// Render n images (n >= 1) that share one form on a context: plan, make
+// room in the context's queues and image table, then launch.
 ask_status render(ask_ctx *ctx, const Image *ims, uint32_t n, uint32_t form, hipStream_t s,
                   ask_stats *stats) {
     // Under stream capture the render becomes a graph that may replay many
-    // times: nothing may wait, allocate or stage data that a later call could
-    // change, and the persistent queue is cleared by a kernel of the graph
+    // times: nothing may wait, nothing a later call could change may be
+    // named, and the persistent queue is cleared by a kernel of the graph
     // (its slots then carry a launch epoch reserved for graphs).
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cap) != hipSuccess) {
@@ -468,42 +642,21 @@ ask_status render(ask_ctx *ctx, const Image *ims, uint32_t n, uint32_t form, hip
         cap = hipStreamCaptureStatusNone;
     }
     const bool capturing = cap != hipStreamCaptureStatusNone;
-    if (capturing && (stats || n > 1 || form == ASK_FORM_LEVELS_READBACK))
+    if (capturing && (stats || form == ASK_FORM_LEVELS_READBACK))
         return fail(ctx, ASK_EINVAL,
-                    "a captured render takes one image, no work counters and not the read-back "
-                    "form%s", nullptr);
-    uint32_t levels = 0;
-    uint64_t nseeds = 0;
-    Bounds b;
-    for (uint32_t i = 0; i < n; ++i) {
-        const Image &im = ims[i];
-        const uint32_t lv_i = add_bounds(im, b);
-        if (lv_i > (uint32_t)kMaxLevels - 1)
-            return fail(ctx, ASK_EINVAL, "too many levels%s", nullptr);
-        levels = std::max(levels, lv_i);
-        nseeds += (uint64_t)im.g * im.g;
-    }
-    if (nseeds > 0x7fffffffull)
-        return fail(ctx, ASK_EINVAL, "too many level-0 regions%s", nullptr);
-    const std::vector<uint64_t> &bound = b.level;
-    uint64_t widest = 0;
-    for (uint32_t lv = 0; lv < levels; ++lv)
-        widest = std::max(widest, bound[lv]);
-    // Per-level form: a level's table holds its regions and the bands of the
-    // leaves decided one level up, at most pixels / (band / 2) plus one per
-    // leaf; bands of last-level leaves take one more level kernel.
-    const bool banded = b.band != ASK_BAND_NONE;
-    const uint64_t band_bound = banded ? b.pixels / (b.band / 2) + widest : 0;
-    const uint64_t need =
-        form == ASK_FORM_PERSISTENT ? b.queue_entries() : widest + band_bound;
-    const uint64_t want = std::min<uint64_t>(need, kQueueBudget);
-    const bool may_overflow = need > want;
+                    "a captured render takes no work counters and not the read-back form%s",
+                    nullptr);
+    Plan p;
+    ask_status st = plan_render(ctx, ims, n, form, p);
+    if (st != ASK_OK)
+        return st;
+    const uint64_t want = std::min<uint64_t>(p.need, kQueueBudget);
+    const bool may_overflow = p.need > want;
     if (capturing && (may_overflow || (form == ASK_FORM_PERSISTENT ? ctx->queue_cap < want
                                                                    : ctx->lvq_cap < want)))
         return fail(ctx, ASK_EINVAL,
                     "render once outside the capture first (the queues must not grow "
                     "while capturing)%s", nullptr);
-    ask_status st;
     if (form == ASK_FORM_PERSISTENT) {
         st = grow(ctx, &ctx->queue, &ctx->queue_cap, want, true);
     } else {
@@ -518,137 +671,93 @@ ask_status render(ask_ctx *ctx, const Image *ims, uint32_t n, uint32_t form, hip
     if (st != ASK_OK)
         return st;
 
-    SubdivArgs a{};
-    a.nimg = n;
-    a.ctrl = ctx->ctrl;
-    a.stats = stats ? ctx->stats : nullptr;
+    Buffers bf;
+    bf.ctrl = ctx->ctrl;
+    bf.stats = stats ? ctx->stats : nullptr;
+    bf.lvq[0] = ctx->lvq[0];
+    bf.lvq[1] = ctx->lvq[1];
+    bf.queue = ctx->queue;
+    bf.cap = form == ASK_FORM_PERSISTENT ? ctx->queue_cap : ctx->lvq_cap;
+    bf.wait_ticks = (uint64_t)(ctx->wait_limit_s * ctx->clock_hz);
+    bf.grid_persistent = (uint32_t)(ctx->cus * ctx->occ_persistent);
+    bf.resident_level = (uint32_t)(ctx->cus * ctx->occ_level);
     hipError_t e = hipSuccess;
-    if (n == 1) {
-        a.single = ims[0];
-    } else {
-        // Image table, then the n + 1 seed offsets, staged through pinned memory.
+    if (n > 1) {
+        // The image table and the n + 1 level-0 seed offsets, written by
+        // kernels that carry them as arguments. A captured batch gets a
+        // table of its own, which no later call writes and the context never
+        // frees before it ends; other batches share the context's table.
+        std::vector<uint32_t> words((n * sizeof(Image) + (n + 1) * sizeof(uint32_t) + 3) / 4);
         const size_t tbytes = (size_t)n * sizeof(Image);
-        const size_t bytes = tbytes + (size_t)(n + 1) * sizeof(uint32_t);
-        if (ctx->staged) {
-            e = hipEventSynchronize(ctx->staged);  // the previous upload has left staging
-            if (e != hipSuccess)
-                return hip_fail(ctx, e, "hipEventSynchronize");
-        }
-        if (ctx->staging_bytes < bytes) {
-            (void)hipHostFree(ctx->staging);
-            ctx->staging = nullptr;
-            ctx->staging_bytes = 0;
-            if (hipHostMalloc(&ctx->staging, bytes, hipHostMallocDefault) != hipSuccess) {
-                (void)hipGetLastError();
-                return fail(ctx, ASK_ENOMEM, "cannot allocate pinned staging memory%s", nullptr);
-            }
-            ctx->staging_bytes = bytes;
-        }
-        if (ctx->table_bytes < bytes) {
-            e = wait_last(ctx);
+        memcpy(words.data(), ims, tbytes);
+        uint32_t *base = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(words.data()) + tbytes);
+        base[0] = 0;
+        for (uint32_t i = 0; i < n; ++i)
+            base[i + 1] = base[i] + ims[i].g * ims[i].g;
+        const size_t bytes = words.size() * sizeof(uint32_t);
+        void *table = nullptr;
+        if (capturing) {
+            // An allocation is not a stream operation: the capture may go on
+            // around it, which the thread's relaxed capture mode permits.
+            hipStreamCaptureMode mode = hipStreamCaptureModeRelaxed;
+            e = hipThreadExchangeStreamCaptureMode(&mode);
             if (e == hipSuccess) {
-                (void)hipFree(ctx->table);
-                ctx->table = nullptr;
-                ctx->table_bytes = 0;
-                e = hipMalloc(&ctx->table, bytes);
+                e = hipMalloc(&table, bytes);
+                hipStreamCaptureMode back = mode;
+                const hipError_t e2 = hipThreadExchangeStreamCaptureMode(&back);
+                if (e == hipSuccess)
+                    e = e2;
             }
+            if (table)
+                ctx->retired.push_back(table);
             if (e != hipSuccess) {
                 (void)hipGetLastError();
                 return fail(ctx, ASK_ENOMEM, "cannot allocate the image table%s", nullptr);
             }
-            ctx->table_bytes = bytes;
+        } else {
+            if (ctx->table_bytes < bytes) {
+                e = wait_last(ctx);
+                if (e == hipSuccess) {
+                    if (ctx->captured)
+                        ctx->retired.push_back(ctx->table);
+                    else
+                        (void)hipFree(ctx->table);
+                    ctx->table = nullptr;
+                    ctx->table_bytes = 0;
+                    e = hipMalloc(&ctx->table, bytes);
+                }
+                if (e != hipSuccess) {
+                    (void)hipGetLastError();
+                    return fail(ctx, ASK_ENOMEM, "cannot allocate the image table%s", nullptr);
+                }
+                ctx->table_bytes = bytes;
+            }
+            table = ctx->table;
         }
-        memcpy(ctx->staging, ims, tbytes);
-        uint32_t *base = reinterpret_cast<uint32_t *>(static_cast<char *>(ctx->staging) + tbytes);
-        base[0] = 0;
-        for (uint32_t i = 0; i < n; ++i)
-            base[i + 1] = base[i] + ims[i].g * ims[i].g;
-        e = hipMemcpyAsync(ctx->table, ctx->staging, bytes, hipMemcpyHostToDevice, s);
-        if (e == hipSuccess)
-            e = hipEventRecord(ctx->staged, s);
+        e = upload_words(static_cast<uint32_t *>(table), words.data(), words.size(), s);
         if (e != hipSuccess)
             return hip_fail(ctx, e, "image table upload");
-        a.table = static_cast<const Image *>(ctx->table);
-        a.seed_base = reinterpret_cast<const uint32_t *>(static_cast<const char *>(ctx->table) + tbytes);
+        bf.table = static_cast<const Image *>(table);
+        bf.seed_base = reinterpret_cast<const uint32_t *>(static_cast<const char *>(table) + tbytes);
     }
-    e = launch_reset(ctx->ctrl, a.stats, s);
-    if (e != hipSuccess)
-        return hip_fail(ctx, e, "reset kernel launch");
-
     if (form == ASK_FORM_PERSISTENT) {
-        uint32_t epoch;
         if (capturing) {
-            ctx->captured = true;
-            e = launch_clear_queue(ctx->queue, (uint32_t)ctx->queue_cap, s);
-            if (e != hipSuccess)
-                return hip_fail(ctx, e, "queue clear launch");
-            epoch = kGraphEpoch;
+            bf.clear_queue = true;
+            bf.epoch = kGraphEpoch;
         } else {
             ctx->epoch = (ctx->epoch + 1) & 0xffffffu;
             if (ctx->epoch == 0 || ctx->epoch == kGraphEpoch) {  // wrapped: clear the queue once
-                e = hipMemsetAsync(ctx->queue, 0, ctx->queue_cap * sizeof(Region), s);
-                if (e != hipSuccess)
-                    return hip_fail(ctx, e, "hipMemsetAsync");
+                bf.clear_queue = true;
                 ctx->epoch = 1;
             }
-            epoch = ctx->epoch;
+            bf.epoch = ctx->epoch;
         }
-        a.queue = ctx->queue;
-        a.cap = (uint32_t)std::min<size_t>(ctx->queue_cap, 0xffffffffu - 65536u);
-        a.epoch = epoch;
-        a.wait_ticks = (uint64_t)(ctx->wait_limit_s * ctx->clock_hz);
-        e = launch_seed_queue(a, (uint32_t)nseeds, s);
-        if (e == hipSuccess)
-            e = mark(ctx, 0, s);
-        if (e == hipSuccess)
-            e = launch_persistent(a, (uint32_t)(ctx->cus * ctx->occ_persistent), s);
-        if (e == hipSuccess)
-            e = mark(ctx, 1, s);
-        if (e != hipSuccess)
-            return hip_fail(ctx, e, "persistent launch");
-    } else {
-        a.cap = (uint32_t)std::min<size_t>(ctx->lvq_cap, 0xffffffffu - 65536u);
-        a.epoch = 0;
-        a.out = ctx->lvq[0];
-        e = launch_seed_levels(a, (uint32_t)nseeds, s);
-        if (e == hipSuccess)
-            e = mark(ctx, 0, s);
-        if (e != hipSuccess)
-            return hip_fail(ctx, e, "seed kernel launch");
-        const uint32_t resident = (uint32_t)(ctx->cus * ctx->occ_level);
-        for (uint32_t lv = 0; lv < levels + (banded ? 1u : 0u); ++lv) {
-            a.level = lv;
-            a.in = ctx->lvq[lv & 1];
-            a.out = ctx->lvq[(lv + 1) & 1];
-            if (form == ASK_FORM_LEVELS_READBACK) {
-                uint32_t cnt = 0;
-                e = hipMemcpyAsync(&cnt, ctx->ctrl + kCount + lv, sizeof(cnt), hipMemcpyDeviceToHost,
-                                   s);
-                if (e == hipSuccess)
-                    e = hipStreamSynchronize(s);
-                if (e != hipSuccess)
-                    return hip_fail(ctx, e, "level count readback");
-                cnt = std::min<uint32_t>(cnt, a.cap);
-                if (cnt == 0)
-                    break;
-                e = launch_level_exact(a, cnt, s);
-            } else {
-                const uint64_t entries = bound[lv] + (lv > 0 ? band_bound : 0);
-                const uint64_t blocks =
-                    std::min<uint64_t>(resident, (entries + kWavesPerBlock - 1) / kWavesPerBlock);
-                e = launch_level(a, (uint32_t)std::max<uint64_t>(1, blocks), s);
-            }
-            if (e != hipSuccess)
-                return hip_fail(ctx, e, "level kernel launch");
-        }
-        e = mark(ctx, 1, s);
-        if (e != hipSuccess)
-            return hip_fail(ctx, e, "hipEventRecord");
     }
-    if (capturing) {
+    if (capturing)
         ctx->captured = true;
-        return ASK_OK;
-    }
+    st = launch_render(ctx, p, bf, ims, n, form, s);
+    if (st != ASK_OK || capturing)
+        return st;
     e = note_last(ctx, s);
     if (e != hipSuccess)
         return hip_fail(ctx, e, "hipEventRecord");
@@ -695,8 +804,40 @@ ask_status ask_dwell_batch(ask_ctx *ctx, uint32_t n, const ask_window *wins,
 ask_status ask_enable_timing(ask_ctx *ctx, int on) {
     if (!ctx)
         return ASK_EINVAL;
+    if (on && ctx->ev.empty()) {
+        DeviceGuard guard(ctx->device);
+        ctx->ev.assign(2 * kTimingRing, nullptr);
+        for (hipEvent_t &ev : ctx->ev) {
+            const hipError_t e = hipEventCreate(&ev);
+            if (e != hipSuccess) {
+                for (hipEvent_t &x : ctx->ev)
+                    if (x)
+                        (void)hipEventDestroy(x);
+                ctx->ev.clear();
+                return hip_fail(ctx, e, "hipEventCreate");
+            }
+        }
+    }
+    if (on && ctx->timing) {  // events of renders still in flight are reused last
+        DeviceGuard guard(ctx->device);
+        const hipError_t e = wait_last(ctx);
+        if (e != hipSuccess)
+            return hip_fail(ctx, e, "hipEventSynchronize");
+    }
     ctx->timing = on != 0;
     ctx->timed = false;
+    ctx->timed_count = 0;
+    return ASK_OK;
+}
+
+// Device time of timed render k (0 = the first since timing was enabled).
+static ask_status kernel_ms(ask_ctx *ctx, uint64_t k, float *ms) {
+    const size_t slot = k % kTimingRing;
+    hipError_t e = hipEventSynchronize(ctx->ev[2 * slot + 1]);
+    if (e == hipSuccess)
+        e = hipEventElapsedTime(ms, ctx->ev[2 * slot], ctx->ev[2 * slot + 1]);
+    if (e != hipSuccess)
+        return hip_fail(ctx, e, "hipEventElapsedTime");
     return ASK_OK;
 }
 
@@ -706,11 +847,22 @@ ask_status ask_last_kernel_ms(ask_ctx *ctx, float *ms) {
     if (!ctx->timed)
         return fail(ctx, ASK_EINVAL, "no timed render on this context%s", nullptr);
     DeviceGuard guard(ctx->device);
-    hipError_t e = hipEventSynchronize(ctx->ev[1]);
-    if (e == hipSuccess)
-        e = hipEventElapsedTime(ms, ctx->ev[0], ctx->ev[1]);
-    if (e != hipSuccess)
-        return hip_fail(ctx, e, "hipEventElapsedTime");
+    return kernel_ms(ctx, ctx->timed_count - 1, ms);
+}
+
+ask_status ask_kernel_times(ask_ctx *ctx, float *ms, uint32_t cap, uint32_t *n) {
+    if (!ctx || !n || (cap && !ms))
+        return ASK_EINVAL;
+    DeviceGuard guard(ctx->device);
+    const uint64_t have = std::min<uint64_t>(ctx->timed_count, kTimingRing);
+    const uint64_t take = std::min<uint64_t>(have, cap);
+    *n = 0;
+    for (uint64_t i = 0; i < take; ++i) {
+        const ask_status st = kernel_ms(ctx, ctx->timed_count - take + i, &ms[i]);
+        if (st != ASK_OK)
+            return st;
+        ++*n;
+    }
     return ASK_OK;
 }
 
@@ -779,6 +931,7 @@ class PoolAlloc {
 };
 
 constexpr uint32_t kMaxGen = (1u << 24) - 1;  // request generations are 24-bit tags
+constexpr size_t kLatencyKept = 1u << 16;     // latencies of this many recent requests are kept
 constexpr uint64_t kDefaultPool = 256ull << 20;
 
 }  // namespace
@@ -801,7 +954,10 @@ struct ask_server {
         uint64_t ticket = 0;
         uint32_t gen = 0;
         uint64_t qoff = 0, qlen = 0;
+        std::chrono::steady_clock::time_point submitted;
     } flight[kMaxSlots];
+    // Latency (s) of the most recent finished requests, by ticket.
+    std::map<uint64_t, double> latency;
     uint32_t next_gen = 1;
     uint64_t next_ticket = 1;
     uint32_t in_flight = 0;
@@ -848,6 +1004,10 @@ void server_reap(ask_server *sv) {
         if (!f.busy || __atomic_load_n(&sv->mb->done[k].gen, __ATOMIC_ACQUIRE) != f.gen)
             continue;
         const int32_t status = __atomic_load_n(&sv->mb->done[k].status, __ATOMIC_RELAXED);
+        sv->latency[f.ticket] =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - f.submitted).count();
+        if (sv->latency.size() > kLatencyKept)
+            sv->latency.erase(sv->latency.begin());
         f.busy = false;
         --sv->in_flight;
         if (status == ASK_OK) {
@@ -1004,6 +1164,7 @@ ask_status ask_server_submit(ask_server *sv, const ask_window *win, const ask_pa
     f.gen = gen;
     f.qoff = qoff;
     f.qlen = qlen;
+    f.submitted = std::chrono::steady_clock::now();
     ++sv->in_flight;
     *ticket = f.ticket;
     return ASK_OK;
@@ -1028,11 +1189,13 @@ ask_status ask_server_reap(ask_server *sv, uint64_t *tickets, int32_t *status, u
     return ASK_OK;
 }
 
-ask_status ask_server_poll(ask_server *sv, uint64_t ticket, int *done) {
+ask_status ask_server_poll(ask_server *sv, uint64_t ticket, int *done, double *latency_s) {
     if (!sv || !done || ticket == 0 || ticket >= sv->next_ticket)
         return ASK_EINVAL;
     DeviceGuard guard(sv->ctx->device);
     server_reap(sv);
+    if (latency_s)
+        *latency_s = -1.0;
     for (uint32_t k = 0; k < sv->nslots; ++k) {
         if (sv->flight[k].busy && sv->flight[k].ticket == ticket) {
             *done = 0;
@@ -1040,6 +1203,11 @@ ask_status ask_server_poll(ask_server *sv, uint64_t ticket, int *done) {
         }
     }
     *done = 1;
+    if (latency_s) {
+        auto lt = sv->latency.find(ticket);
+        if (lt != sv->latency.end())
+            *latency_s = lt->second;
+    }
     auto it = sv->failed.find(ticket);
     return it == sv->failed.end() ? ASK_OK : (ask_status)it->second;
 }

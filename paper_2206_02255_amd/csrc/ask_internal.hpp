@@ -21,6 +21,9 @@ struct Image {
                               // 1: the pixel's point is z_0, c = (jr, ji) (filled Julia set)
     uint32_t band;            // queue forms: leaves above band pixels go out as row bands
                               // of about band pixels; others are computed whole
+    uint32_t tile_w, tile_h;  // pixel tile of one wave (tile_w * tile_h = 64): the exhaustive
+                              // kernel's wave tile; leaf pixels are streamed tile by tile
+                              // (tile_w == 0: leaves stream row by row)
     uint32_t *out;            // W*H dwell image, row-major, row 0 on the y0 side
 };
 
@@ -59,6 +62,9 @@ struct DevStats {
     unsigned long long leaves[kMaxLevels];
     unsigned long long iters_ring;
     unsigned long long iters_leaf;
+    unsigned long long ring_px;   // ring sizes summed over scanned regions
+    unsigned long long leaf_px;   // pixels of leaf regions
+    unsigned long long fill_px;   // pixels of filled regions
     uint32_t levels;
     uint32_t overflow;
 };
@@ -159,7 +165,17 @@ struct ServerArgs {
 hipError_t launch_server(const ServerArgs &a, uint32_t grid_blocks, hipStream_t s);
 hipError_t occupancy_server(int *blocks_per_cu);
 
+// Up to kWordsPerWrite words of data carried in one kernel's arguments and
+// stored at dst (image tables of batches: a captured launch keeps its data).
+constexpr uint32_t kWordsPerWrite = 896;
+struct WordsArg {
+    uint32_t *dst;
+    uint32_t n;
+    uint32_t words[kWordsPerWrite];
+};
+
 // Kernel launchers (ask_kernels.hip). All return hipSuccess or the launch error.
+hipError_t launch_write_words(const WordsArg &w, hipStream_t s);
 hipError_t launch_exhaustive(const Image &im, hipStream_t s);
 hipError_t launch_reset(uint32_t *ctrl, DevStats *stats, hipStream_t s);
 hipError_t launch_clear_queue(Region *queue, uint32_t entries, hipStream_t s);

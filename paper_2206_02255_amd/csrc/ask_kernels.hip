@@ -182,14 +182,18 @@ __device__ __forceinline__ void put_dwell(uint32_t *out, size_t i, uint32_t d) {
 }
 
 // ---------------------------------------------------------------------------
-// Exhaustive image (Sec. 4.1): one lane per pixel. A 256-lane workgroup owns
-// a 16 x 16 tile; each wave a 16 x 4 strip of it.
+// Exhaustive image (Sec. 4.1): one lane per pixel. Each wave owns a tile of
+// kTileW x (64 / kTileW) pixels, and a 256-lane workgroup four such tiles
+// stacked vertically (the default 16 x 4 wave tile makes 16 x 16 workgroup
+// tiles, the paper's best block for this kernel).
 // ---------------------------------------------------------------------------
+template <uint32_t kTileW>
 __global__ __launch_bounds__(kBlock) void exhaustive_kernel(Image im) {
+    constexpr uint32_t kTileH = kWave / kTileW;
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = threadIdx.x / kWave;
-    const uint32_t px = blockIdx.x * 16 + (lane & 15);
-    const uint32_t py = blockIdx.y * 16 + wave * 4 + (lane >> 4);
+    const uint32_t px = blockIdx.x * kTileW + (lane % kTileW);
+    const uint32_t py = (blockIdx.y * kWavesPerBlock + wave) * kTileH + lane / kTileW;
     if (px >= im.W || py >= im.H)
         return;
     double zr, zi, cr, ci;
@@ -216,37 +220,40 @@ __global__ __launch_bounds__(kBlock) void exhaustive_kernel(Image im) {
 // once per round.
 //
 // pixel_of(i, px, py) names pixel i of the stream (false: no pixel there);
-// done(px, py, dwell) is called by the lane that finished a pixel.
+// done(px, py, dwell, ring) is called by the lane that finished a pixel,
+// ring telling whether it was one of the first n_ring stream positions.
 //
-// Border streams (WaveBorder) also decide uniformity, and stop as soon as the
-// border is known to be mixed: once some pixel has finished with dwell v (the
-// least dwell of the first round in which any pixel finished), the border is
-// mixed if another pixel finishes with a different dwell, or if a pixel still
-// running has already done v iterations (its dwell is larger than v). The
-// decision is the same as after the whole border; only the remaining
-// iterations are saved. The return value is then false; for a border whose
-// every pixel finished with v it is true.
-// `partial` receives, per lane, the iterations of a pixel left unfinished by
-// an early stop (work done, for the counters).
+// A leaf stream (kRing false) computes positions [0, n_all). A ring stream
+// (kRing true) takes the border first, positions [0, n_ring), and decides
+// uniformity as it goes, so that it can stop as soon as the border is known
+// to be mixed: once some pixel has finished with dwell v (the least dwell of
+// the first round in which any pixel finished), the border is mixed if
+// another pixel finishes with a different dwell, or if a pixel still running
+// has already done v iterations (its dwell is larger than v). The decision
+// is the one the whole border would give.
+//   - n_all == n_ring: the stream stops there; `partial` receives, per lane,
+//     the iterations of a pixel left unfinished (work done, for counters).
+//   - n_all > n_ring (a leaf-size region whose wave computes the leaf): the
+//     stream goes on after a mixed decision with the border's remaining
+//     positions and then positions [n_ring, n_all), the leaf's inside, so no
+//     finished border dwell is recomputed and no lane's work is dropped.
+// Returns kUniform for a border whose every pixel finished with v, kMixed
+// for a mixed border that stopped, kLeafDone for a mixed border whose leaf
+// the stream then completed (and kLeafDone for leaf streams).
 // ---------------------------------------------------------------------------
 constexpr uint32_t kRoundBlocks = 4;
 
-// Border policies of dwell_stream: a leaf stream has none; a ring stream
-// decides uniformity against its first finished dwell.
-struct NoBorder {
-    static constexpr bool kActive = false;
-};
+enum StreamEnd : uint32_t { kUniform = 0, kMixed = 1, kLeafDone = 2 };
 
-struct WaveBorder {
-    static constexpr bool kActive = true;
-};
-
-template <class Border, class PixelOf, class Done>
-__device__ __forceinline__ bool dwell_stream(const Image &im, uint32_t n, PixelOf pixel_of,
-                                             Done done, Border, uint32_t &v, uint32_t &partial) {
+template <bool kRing, class PixelOf, class Done>
+__device__ __forceinline__ uint32_t dwell_stream(const Image &im, uint32_t n_ring, uint32_t n_all,
+                                                 PixelOf pixel_of, Done done, uint32_t &v,
+                                                 uint32_t &partial) {
     const uint32_t D = im.D;
     uint32_t next = 0;  // first stream index no lane has taken yet (uniform)
-    bool have = false, special = false, vset = false;
+    uint32_t n = kRing ? n_ring : n_all;  // end of the stream as far as it is known to run
+    bool scanning = kRing;                // the border's uniformity is still undecided
+    bool have = false, special = false, vset = false, ring = false;
     uint32_t px = 0, py = 0, kbase = 0;
     double cr = 0.0, ci = 0.0, zr = 0.0, zi = 0.0, zr2 = 0.0, zi2 = 0.0;
     partial = 0;
@@ -260,6 +267,7 @@ __device__ __forceinline__ bool dwell_stream(const Image &im, uint32_t n, PixelO
                 const uint32_t j = next + lane_rank(idle);
                 if (j < n && pixel_of(j, px, py)) {
                     have = true;
+                    ring = kRing && j < n_ring;
                     pixel_orbit(im, px, py, zr, zi, cr, ci);
                     special = !(cr * cr + ci * ci <= 3.99);
                     zr2 = zr * zr;
@@ -331,22 +339,26 @@ __device__ __forceinline__ bool dwell_stream(const Image &im, uint32_t n, PixelO
             }
             if (fin) {
                 dw = dw > D ? D : dw;
-                done(px, py, dw);
+                done(px, py, dw, ring);
                 have = false;
             }
         }
-        if (Border::kActive) {
+        if (kRing && scanning) {
             if (!vset && __ballot(fin)) {
                 v = uniform(wave_min(fin ? dw : 0xffffffffu));
                 vset = true;
             }
             if (vset && __ballot((fin && dw != v) || (have && kbase >= v))) {
-                partial = have ? kbase : 0u;
-                return false;
+                if (n_all == n_ring) {
+                    partial = have ? kbase : 0u;
+                    return kMixed;
+                }
+                scanning = false;  // mixed: go on as the leaf
+                n = n_all;
             }
         }
     }
-    return true;
+    return (kRing && scanning) ? kUniform : kLeafDone;
 }
 
 // ---------------------------------------------------------------------------
@@ -406,25 +418,51 @@ __device__ void fill_region(uint32_t *out, uint32_t W, uint32_t x, uint32_t y, u
     }
 }
 
-// Last-level work L: the dwell of every pixel of the region, row-major, as
-// one refilled stream.
-__device__ unsigned long long leaf_region(const Image &im, uint32_t x, uint32_t y, uint32_t w,
-                                          uint32_t h) {
-    unsigned long long it = 0;
-    uint32_t v, partial;
-    dwell_stream(
-        im, w * h,
-        [&](uint32_t i, uint32_t &px, uint32_t &py) {
+// Pixel order of a rectangle [x, x+w) x [y, y+h) as a stream: row-major, or
+// tile by tile when the image sets a wave tile (tiles of tile_w x tile_h
+// pixels in row-major order over the rectangle, pixels row-major within a
+// tile, positions beyond the rectangle's right or bottom edge passed over).
+struct RectOrder {
+    uint32_t x, y, w, h, tw, sh, th, ntx;
+    __device__ RectOrder(const Image &im, uint32_t x_, uint32_t y_, uint32_t w_, uint32_t h_)
+        : x(x_), y(y_), w(w_), h(h_), tw(im.tile_w),
+          sh(im.tile_w ? (uint32_t)__builtin_ctz(im.tile_w) : 0u),
+          th(im.tile_w ? (kWave >> sh) : 1u), ntx(im.tile_w ? (w_ + im.tile_w - 1) >> sh : 1u) {}
+    // Stream positions (pixels, and passed-over positions of partial tiles).
+    __device__ uint32_t positions() const {
+        return tw ? ntx * ((h + th - 1) / th) * kWave : w * h;
+    }
+    __device__ bool pixel(uint32_t i, uint32_t &px, uint32_t &py) const {
+        if (tw == 0) {
             const uint32_t row = i / w;
             px = x + (i - row * w);
             py = y + row;
             return true;
-        },
-        [&](uint32_t px, uint32_t py, uint32_t d) {
+        }
+        const uint32_t t = i / kWave, p = i % kWave;
+        const uint32_t ty = t / ntx, tx = t - ty * ntx;
+        const uint32_t cx = (tx << sh) + (p & (tw - 1)), cy = ty * th + (p >> sh);
+        px = x + cx;
+        py = y + cy;
+        return cx < w && cy < h;
+    }
+};
+
+// Last-level work L for a band of a leaf: the dwell of every pixel of the
+// rectangle as one refilled stream.
+__device__ unsigned long long leaf_region(const Image &im, uint32_t x, uint32_t y, uint32_t w,
+                                          uint32_t h) {
+    unsigned long long it = 0;
+    uint32_t v, partial;
+    const RectOrder order(im, x, y, w, h);
+    dwell_stream<false>(
+        im, 0u, order.positions(),
+        [&](uint32_t i, uint32_t &px, uint32_t &py) { return order.pixel(i, px, py); },
+        [&](uint32_t px, uint32_t py, uint32_t d, bool) {
             put_dwell(im.out, (size_t)py * im.W + px, d);
             it += d;
         },
-        NoBorder{}, v, partial);
+        v, partial);
     return it;
 }
 
@@ -450,6 +488,8 @@ __device__ __forceinline__ Image image_of(const SubdivArgs &a, uint32_t img) {
         im.ji = t.ji;
         im.julia = t.julia;
         im.band = t.band;
+        im.tile_w = t.tile_w;
+        im.tile_h = t.tile_h;
         im.out = t.out;
         return im;
     }
@@ -547,28 +587,31 @@ __device__ void queue_leaf_bands(const SubdivArgs &a, uint32_t img, uint32_t x, 
 template <bool kQueue>
 __device__ void decide_region(const SubdivArgs &a, uint32_t img, const Image &im, uint32_t x,
                               uint32_t y, uint32_t w, uint32_t h, uint32_t level,
-                              bool uniform_ring, uint32_t v, uint32_t lane) {
+                              uint32_t outcome, uint32_t v, uint32_t lane) {
     DevStats *st = a.stats;
+    const unsigned long long area = (unsigned long long)w * h;
     if (st) {
         wave_add64(&st->regions[level], 1ull);
+        wave_add64(&st->ring_px, ring_size(w, h));
         wave_max(&st->levels, level + 1);
     }
-    if (uniform_ring) {
+    if (outcome == kUniform) {
         fill_region(im.out, im.W, x, y, w, h, v, lane);
-        if (st)
+        if (st) {
             wave_add64(&st->fills[level], 1ull);
+            wave_add64(&st->fill_px, area);
+        }
         return;
     }
     if (w <= im.B && h <= im.B) {
-        if (st)
+        if (st) {
             wave_add64(&st->leaves[level], 1ull);
-        if (w * h > im.band) {
-            queue_leaf_bands<kQueue>(a, img, x, y, w, h, im.band, level, lane);
-            return;
+            wave_add64(&st->leaf_px, area);
         }
-        unsigned long long li = leaf_region(im, x, y, w, h);
-        if (st)
-            wave_add64(&st->iters_leaf, wave_sum(li));
+        // The ring stream has computed a leaf the wave keeps; a larger one
+        // (64-bit area: a 65536 x 65536 leaf has 2^32 pixels) goes out as bands.
+        if (outcome != kLeafDone)
+            queue_leaf_bands<kQueue>(a, img, x, y, w, h, im.band, level, lane);
         return;
     }
     if (level + 1 >= kMaxLevels) {  // unreachable for valid sizes; never write past the tables
@@ -589,18 +632,32 @@ __device__ void decide_region(const SubdivArgs &a, uint32_t img, const Image &im
 // mixed as soon as one of its pixels has a dwell other than the rest; on a
 // ring whose pixels mostly run to D this finds a short arc of other dwells
 // in a few rounds rather than after up to q rounds of D iterations each, and
-// those rings are the ones a split must wait for. Returns whether every ring
-// pixel finished with dwell v; adds the iterations done to the counters.
-__device__ bool scan_ring(const SubdivArgs &a, const Image &im, uint32_t x, uint32_t y,
-                          uint32_t w, uint32_t h, uint32_t &v) {
+// those rings are the ones a split must wait for.
+//
+// Every finished ring dwell is written to the image: a pixel on a scanned
+// ring ends up with its own dwell whatever follows (a fill of that ring
+// writes the same value; a split puts the pixel on a child's ring), so the
+// write is never wrong and a leaf need not compute it again. When `leaf` is
+// set (a leaf-size region the wave computes itself), a mixed ring goes on
+// into the leaf's inside in the same stream. Returns the stream's outcome
+// (kUniform with v, kMixed, kLeafDone) and adds the iterations done to the
+// counters: ring pixels to the ring's, inside pixels to the leaves'.
+__device__ uint32_t scan_ring(const SubdivArgs &a, const Image &im, uint32_t x, uint32_t y,
+                              uint32_t w, uint32_t h, bool leaf, uint32_t &v) {
     const uint32_t nring = ring_size(w, h);
     const uint32_t q = (nring + kWave - 1) / kWave;
     const uint32_t bits = q > 1 ? 32u - (uint32_t)__builtin_clz(q - 1) : 0u;  // 2^bits >= q
-    unsigned long long it = 0;
+    const uint32_t n_ring = kWave << bits;
+    const bool inside = leaf && w > 2 && h > 2;
+    const RectOrder order(im, x + 1, y + 1, inside ? w - 2 : 1u, inside ? h - 2 : 1u);
+    const uint32_t n_all = n_ring + (inside ? order.positions() : 0u);
+    unsigned long long it_ring = 0, it_leaf = 0;
     uint32_t partial = 0;
-    const bool same = dwell_stream(
-        im, kWave << bits,
+    const uint32_t outcome = dwell_stream<true>(
+        im, n_ring, leaf ? max(n_all, n_ring + 1u) : n_ring,
         [&](uint32_t j, uint32_t &px, uint32_t &py) {
+            if (j >= n_ring)
+                return j < n_all && order.pixel(j - n_ring, px, py);
             const uint32_t round = j / kWave;
             const uint32_t off = bits ? __brev(round) >> (32u - bits) : 0u;
             const uint32_t t = (j % kWave) * q + off;
@@ -609,10 +666,20 @@ __device__ bool scan_ring(const SubdivArgs &a, const Image &im, uint32_t x, uint
             ring_pixel(x, y, w, h, t, px, py);
             return true;
         },
-        [&](uint32_t, uint32_t, uint32_t d) { it += d; }, WaveBorder{}, v, partial);
-    if (a.stats)
-        wave_add64(&a.stats->iters_ring, wave_sum(it + partial));
-    return same;
+        [&](uint32_t px, uint32_t py, uint32_t d, bool ring) {
+            put_dwell(im.out, (size_t)py * im.W + px, d);
+            if (ring)
+                it_ring += d;
+            else
+                it_leaf += d;
+        },
+        v, partial);
+    if (a.stats) {
+        wave_add64(&a.stats->iters_ring, wave_sum(it_ring + partial));
+        if (leaf)
+            wave_add64(&a.stats->iters_leaf, wave_sum(it_leaf));
+    }
+    return outcome;
 }
 
 // One region, by one wave: border query Q, then fill T, leaf L or split S
@@ -631,9 +698,12 @@ __device__ void process_region(const SubdivArgs &a, const Region &R, uint32_t la
             wave_add64(&a.stats->iters_leaf, wave_sum(li));
         return;
     }
+    // A leaf-size region whose leaf this wave computes: its ring stream goes
+    // on into the leaf when the ring is mixed.
+    const bool leaf = w <= im.B && h <= im.B && (unsigned long long)w * h <= im.band;
     uint32_t v = 0;
-    const bool same = scan_ring(a, im, x, y, w, h, v);
-    decide_region<kQueue>(a, img, im, x, y, w, h, level, same, v, lane);
+    const uint32_t outcome = scan_ring(a, im, x, y, w, h, leaf, v);
+    decide_region<kQueue>(a, img, im, x, y, w, h, level, outcome, v, lane);
 }
 
 // Per-level kernel: waves take the level's regions one at a time through an
@@ -1042,6 +1112,12 @@ __global__ void clear_queue_kernel(uint4 *q, uint32_t entries) {
         q[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
+// Data carried in the launch's arguments, stored to device memory.
+__global__ void write_words_kernel(WordsArg w) {
+    for (uint32_t i = threadIdx.x; i < w.n; i += blockDim.x)
+        w.dst[i] = w.words[i];
+}
+
 // Level 0 (Sec. 4.2: G = g x g initial regions): the floor partition of each
 // image. Seed i belongs to the image whose seed range holds it.
 template <bool kQueue>
@@ -1087,9 +1163,26 @@ __global__ void seed_kernel(SubdivArgs a, uint32_t nseeds) {
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
+template <uint32_t kTileW>
+static hipError_t launch_exhaustive_tile(const Image &im, hipStream_t s) {
+    constexpr uint32_t rows = kWavesPerBlock * (kWave / kTileW);  // pixel rows per workgroup
+    dim3 grid((im.W + kTileW - 1) / kTileW, (im.H + rows - 1) / rows);
+    hipLaunchKernelGGL(exhaustive_kernel<kTileW>, grid, dim3(kBlock), 0, s, im);
+    return hipGetLastError();
+}
+
 hipError_t launch_exhaustive(const Image &im, hipStream_t s) {
-    dim3 grid((im.W + 15) / 16, (im.H + 15) / 16);
-    hipLaunchKernelGGL(exhaustive_kernel, grid, dim3(kBlock), 0, s, im);
+    switch (im.tile_w) {
+    case 4: return launch_exhaustive_tile<4>(im, s);
+    case 8: return launch_exhaustive_tile<8>(im, s);
+    case 32: return launch_exhaustive_tile<32>(im, s);
+    case 64: return launch_exhaustive_tile<64>(im, s);
+    default: return launch_exhaustive_tile<16>(im, s);
+    }
+}
+
+hipError_t launch_write_words(const WordsArg &w, hipStream_t s) {
+    hipLaunchKernelGGL(write_words_kernel, dim3(1), dim3(kBlock), 0, s, w);
     return hipGetLastError();
 }
 

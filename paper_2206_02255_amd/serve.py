@@ -60,20 +60,22 @@ class Arena(FirstFit):
 
 
 def serve(ctx, schedule, params_of, slots=64, arena_bytes=16 << 30, pool_bytes=1 << 30,
-          keep=None, log=None, limit_s=120.0):
+          keep=None, log=None, limit_s=120.0, probe=None):
     """Run `schedule` [(arrival_s, window)] through a server on ctx.
 
     params_of(window) -> workloads.Params. keep(i) -> True to copy request
-    i's image to the host (returned in 'images'). Raises TimeoutError when
-    the run lasts limit_s beyond the last arrival. Returns a dict of the
-    run's measurements."""
+    i's image to the host (returned in 'images'). probe(i, image) is called
+    with request i's finished image (a flat device tensor view, valid only
+    during the call); its results are returned in 'probes'. Raises
+    TimeoutError when the run lasts limit_s beyond the last arrival. Returns
+    a dict of the run's measurements."""
     import torch
     arena = Arena(torch, arena_bytes // 4)
     torch.cuda.current_stream().synchronize()
     sv = ask.ask_server_create(ctx, slots=slots, pool_bytes=pool_bytes)
     backlog = collections.deque()
     inflight = {}
-    lat, peak, images, failed = [], 0, {}, 0
+    lat, peak, images, failed, probes = [], 0, {}, 0, {}
     done_px = 0
     n = len(schedule)
     i = 0
@@ -111,6 +113,8 @@ def serve(ctx, schedule, params_of, slots=64, arena_bytes=16 << 30, pool_bytes=1
                 failed += st != 0
                 if keep is not None and keep(j):
                     images[j] = arena.t[off:off + w.pixels].cpu().numpy().view(np.uint32).reshape(w.H, w.W)
+                if probe is not None:
+                    probes[j] = probe(j, arena.t[off:off + w.pixels])
                 arena.release(off, w.pixels)
             if log and time.perf_counter() - last_log > 5.0:
                 last_log = time.perf_counter()
@@ -132,7 +136,7 @@ def serve(ctx, schedule, params_of, slots=64, arena_bytes=16 << 30, pool_bytes=1
             "latency_p50_ms": float(np.percentile(lat, 50) * 1e3),
             "latency_p99_ms": float(np.percentile(lat, 99) * 1e3),
             "latency_max_ms": float(lat.max() * 1e3),
-            "peak_in_flight": peak, "slots": slots, "images": images}
+            "peak_in_flight": peak, "slots": slots, "images": images, "probes": probes}
 
 
 def sequential(ctx, windows, params_of, form="levels"):

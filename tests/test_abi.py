@@ -64,6 +64,11 @@ def test_validation(ask):
     bad = ask.window(Window(-1, 1, -1, 1, 8, 8, 10))
     bad.set = 2
     assert ask.ask_validate(bad) == ask.EINVAL
+    # wave tiles: both 0, or a power-of-two width 4..64 holding exactly 64 pixels
+    for tile in ((0, 0), (4, 16), (8, 8), (16, 4), (32, 2), (64, 1)):
+        assert ask.ask_validate(good, ask.params(4, 2, 8, "levels", 0, tile)) == 0, tile
+    for tile in ((0, 4), (16, 0), (2, 32), (128, 1), (12, 5), (16, 8), (8, 4), (1, 64)):
+        assert ask.ask_validate(good, ask.params(4, 2, 8, "levels", 0, tile)) == ask.EINVAL, tile
 
 
 def test_level_count_bounds_the_oracle_depth(ask, ref):
@@ -100,6 +105,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     fields = {"ask_window": [f for f, _ in ask.ask_window._fields_],
               "ask_params": [f for f, _ in ask.ask_params._fields_],
+              "ask_stats": [f for f, _ in ask.ask_stats._fields_],
               "ask_server_cfg": [f for f, _ in ask.ask_server_cfg._fields_],
               "ask_volume": [f for f, _ in ask.ask_volume._fields_],
               "ask3_params": [f for f, _ in ask.ask3_params._fields_],

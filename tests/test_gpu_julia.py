@@ -91,7 +91,7 @@ def test_julia_subdiv(gpu, ref, form):
             for k in ("regions", "fills", "splits", "leaves"):
                 assert st[k][:n] == rst[k][:n], k
             assert rst["iters_ring_filled"] <= st["iters_ring"] <= rst["iters_ring"]
-            assert st["iters_leaf"] == rst["iters_leaf"]
+            assert rst["iters_leaf_inner"] <= st["iters_leaf"] <= rst["iters_leaf"]
             assert st["overflow"] == 0
 
 

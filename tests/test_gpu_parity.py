@@ -37,32 +37,42 @@ def _host(torch, t, w):
     return t.cpu().numpy().view(np.uint32).reshape(w.H, w.W)
 
 
-def gpu_exhaustive(gpu, w):
+def gpu_exhaustive(gpu, w, tile=None):
     ask, ctx, torch = gpu
     out = _out(torch, w)
     ask.ask_dwell_exhaustive(ctx, ask.window(w), out.data_ptr(),
-                             torch.cuda.current_stream().cuda_stream)
+                             torch.cuda.current_stream().cuda_stream, tile=tile)
     return _host(torch, out, w)
 
 
-def gpu_subdiv(gpu, w, g, r, B, form, stats=True):
+def gpu_subdiv(gpu, w, g, r, B, form, stats=True, band=0, tile=(0, 0)):
     ask, ctx, torch = gpu
     out = _out(torch, w)
-    st = ask.ask_dwell_subdiv(ctx, ask.window(w), ask.params(g, r, B, form), out.data_ptr(),
-                              torch.cuda.current_stream().cuda_stream, want_stats=stats)
+    st = ask.ask_dwell_subdiv(ctx, ask.window(w), ask.params(g, r, B, form, band, tile),
+                              out.data_ptr(), torch.cuda.current_stream().cuda_stream,
+                              want_stats=stats)
     return _host(torch, out, w), st
 
 
-def assert_same_stats(st, ref_st):
+def assert_same_stats(st, ref_st, no_bands=False):
     n = ref_st["levels"]
     assert st["levels"] == n
     for k in ("regions", "fills", "splits", "leaves"):
         assert st[k][:n] == ref_st[k][:n], k
     # A ring scan stops once the ring is known to be mixed, so the GPU computes
     # at most the oracle's ring iterations and at least those of the rings of
-    # filled regions, which must be computed whole; leaves are computed whole.
+    # filled regions, which must be computed whole. A leaf keeps its ring's
+    # dwells and computes its inside; a leaf cut into bands computes every
+    # pixel of its bands.
     assert ref_st["iters_ring_filled"] <= st["iters_ring"] <= ref_st["iters_ring"]
-    assert st["iters_leaf"] == ref_st["iters_leaf"]
+    assert ref_st["iters_leaf_inner"] <= st["iters_leaf"] <= ref_st["iters_leaf"]
+    if no_bands:
+        # every leaf's ring is computed whole, once, and its inside once
+        leaf_rings = ref_st["iters_leaf"] - ref_st["iters_leaf_inner"]
+        assert st["iters_leaf"] == ref_st["iters_leaf_inner"]
+        assert ref_st["iters_ring_filled"] + leaf_rings <= st["iters_ring"]
+    for k in ("ring_px", "leaf_px", "fill_px"):
+        assert st[k] == ref_st[k], k
     assert st["overflow"] == 0
 
 
@@ -153,7 +163,7 @@ def test_subdiv_small_paper_window(gpu, ref, form):
     img, st = gpu_subdiv(gpu, SMALL, p.g, p.r, p.B, form)
     want, ref_st = ref.subdiv(SMALL, p.g, p.r, p.B)
     assert np.array_equal(img, want)
-    assert_same_stats(st, ref_st)
+    assert_same_stats(st, ref_st, no_bands=True)  # B = 32: 1024-pixel leaves, no bands
 
 
 @pytest.mark.parametrize("form", FORMS)
@@ -315,4 +325,98 @@ def test_leaf_bands(gpu, ref, form, band):
                                   want_stats=True)
         want, rst = ref.subdiv(w, g, r, B)
         assert np.array_equal(_host(torch, out, w), want), (w, band)
-        assert_same_stats(st, rst)
+        assert_same_stats(st, rst, no_bands=band == 0xffffffff or B * B <= band)
+
+
+TILES = [(4, 16), (8, 8), (16, 4), (32, 2), (64, 1)]
+
+
+@pytest.mark.parametrize("tile", TILES)
+def test_exhaustive_wave_tiles(gpu, ref, tile):
+    """Every wave tile gives the oracle's image: ragged windows (partial
+    tiles on the right and bottom edges) and the 1024 x 1024 paper window."""
+    for w in EDGE_WINDOWS + random_windows(33, 8, max_side=200, max_dwell=1000) + [SMALL]:
+        assert np.array_equal(gpu_exhaustive(gpu, w, tile), ref.exhaustive(w)[0]), (tile, w)
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("tile", [(4, 16), (8, 8), (32, 2), (64, 1)])
+def test_subdiv_wave_tiles(gpu, ref, form, tile):
+    """Leaf pixels streamed tile by tile: the oracle's image and counters,
+    for whole leaves and for leaf bands."""
+    cases = [(w, p) for i, w in enumerate(random_windows(43, 6, max_side=160, max_dwell=1500))
+             for p in random_params(900 + i, w, 2)]
+    cases.append((SMALL, SMALL_PARAMS))
+    for w, p in cases:
+        want, rst = ref.subdiv(w, p.g, p.r, p.B)
+        for band in (0xffffffff, 64, 0):
+            img, st = gpu_subdiv(gpu, w, p.g, p.r, p.B, form, band=band, tile=tile)
+            assert np.array_equal(img, want), (tile, w, p, band)
+            assert_same_stats(st, rst)
+
+
+def test_kernel_times_of_consecutive_renders(gpu):
+    """The context times the dominant kernel of every timed render: one
+    positive device time per render, in order, no more than the ring holds."""
+    ask, ctx, torch = gpu
+    w = paper_window(1024, 512)
+    out = _out(torch, w)
+    s = torch.cuda.current_stream().cuda_stream
+    ask.ask_enable_timing(ctx, True)
+    try:
+        for _ in range(5):
+            ask.ask_dwell_subdiv(ctx, ask.window(w), ask.params(8, 2, 16, "persistent"),
+                                 out.data_ptr(), s)
+        ms = ask.ask_kernel_times(ctx)
+        assert len(ms) == 5 and all(m > 0 for m in ms)
+        assert ask.ask_last_kernel_ms(ctx) == ms[-1]
+        for _ in range(300):
+            ask.ask_dwell_exhaustive(ctx, ask.window(paper_window(64, 16)), out.data_ptr(), s)
+        assert len(ask.ask_kernel_times(ctx, cap=1000)) == 256
+        assert len(ask.ask_kernel_times(ctx, cap=3)) == 3
+    finally:
+        ask.ask_enable_timing(ctx, False)
+        ask.ask_synchronize(ctx, s)
+
+
+def test_context_with_preallocated_queues(ref):
+    """A context created with queue memory set aside renders the same images."""
+    import torch
+    from paper_2206_02255_amd import ask
+    ctx = ask.ask_create(0, queue_bytes=8 << 20)
+    try:
+        g = (ask, ctx, torch)
+        for form in FORMS:
+            img, st = gpu_subdiv(g, SMALL, 4, 2, 32, form)
+            want, rst = ref.subdiv(SMALL, 4, 2, 32)
+            assert np.array_equal(img, want)
+            assert_same_stats(st, rst)
+    finally:
+        ask.ask_destroy(ctx)
+
+
+@pytest.mark.parametrize("form,band", [("persistent", 0xffffffff), ("levels", 0)])
+def test_one_leaf_of_65536_squared(gpu, ref, form, band):
+    """W = H = 65536, g = 1, B = 65536: the whole image is one leaf of 2^32
+    pixels (cut into bands of 2^24 pixels even without banding). Every pixel is written
+    and sampled pixels equal the oracle's (the paper's largest n, Sec. 6.1)."""
+    ask, ctx, torch = gpu
+    w = paper_window(65536, 24)
+    out = torch.zeros(w.W * w.H, dtype=torch.int32, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    print(form, band, w, flush=True)
+    st = ask.ask_dwell_subdiv(ctx, ask.window(w), ask.params(1, 2, 65536, form, band),
+                              out.data_ptr(), s, want_stats=True)
+    assert st["leaves"][0] == 1 and st["leaf_px"] == 1 << 32 and st["overflow"] == 0
+    assert int((out == 0).sum().item()) == 0
+    rng = np.random.default_rng(65536)
+    px = rng.integers(0, w.W, 2000).astype(np.int64)
+    py = rng.integers(0, w.H, 2000).astype(np.int64)
+    idx = torch.as_tensor(py * w.W + px, device="cuda")
+    got = out[idx].cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, ref.subdiv_pixels(w, 1, 2, 65536, px, py))
+    corners = torch.as_tensor([0, w.W - 1, (w.H - 1) * w.W, w.W * w.H - 1], device="cuda")
+    cpx, cpy = np.array([0, w.W - 1, 0, w.W - 1]), np.array([0, 0, w.H - 1, w.H - 1])
+    assert np.array_equal(out[corners].cpu().numpy().view(np.uint32),
+                          ref.subdiv_pixels(w, 1, 2, 65536, cpx, cpy))
+    del out

@@ -98,8 +98,9 @@ def test_results_equal_alone_and_in_the_mix(env, ref):
         for t, i in tickets.items():
             w = reqs[i][0]
             assert np.array_equal(_host(outs[i], w), alone[i]), i
-            done, st = ask.ask_server_poll(sv, t)
+            done, st, lat = ask.ask_server_poll(sv, t)
             assert done and st == 0
+            assert lat is not None and 0.0 <= lat < 60.0
     finally:
         ask.ask_server_destroy(sv)
 

@@ -182,6 +182,12 @@ VOLUME = Volume(-1.6, 1.6, -1.6, 1.6, -1.6, 1.6, 512, 512, 512, 256, c=VOLUME_C)
 VOLUME_PARAMS = Params(32, 2, 8)
 
 
+def rule_params(side, s0, r, B):
+    """(g, r, B) for an image of the given side under a per-image rule:
+    level-0 regions of about s0 pixels (g = side // s0, clamped to [1, 256])."""
+    return Params(max(1, min(256, side // s0)), r, B)
+
+
 def batch_params(side):
     """(g, r, B) for a batch or serving image of the given side: level-0
     regions of about 256 pixels, r = 2, B = 128. These images zoom onto the
