@@ -207,6 +207,31 @@ ask_status ask_dwell_subdiv(ask_ctx *ctx, const ask_window *win,
                             const ask_params *params, uint32_t *d_out,
                             void *stream, ask_stats *stats);
 
+/* Device memory, in bytes, that ask_dwell_subdiv_noalloc works in: one
+ * array per device, held from the library's first use on that device until
+ * the process ends. */
+#define ASK_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* For callers that cannot allocate (code under graph capture, tight serving
+ * loops, harnesses that forbid allocation): the subdivision image of
+ * ask_dwell_subdiv, bit for bit, without a context and without allocating
+ * anything. The render's control words and region queue live in a fixed
+ * array of ASK_NOALLOC_SCRATCH_BYTES of device memory on the current HIP
+ * device; the call only launches kernels on `stream` and returns.
+ * params->form: ASK_FORM_LEVELS or ASK_FORM_PERSISTENT. A window whose worst
+ * case does not fit the array (for the persistent form, the queue bound of
+ * ask_dwell_subdiv: 16 bytes per region a render can reach and per leaf band;
+ * for the per-level form, two tables of the widest level) is refused with
+ * ASK_EINVAL, so no queue can overflow. Every call on a device shares that
+ * device's array, which keeps the last call's contents (each call clears
+ * what it needs): calls that overlap on one device race and give invalid
+ * images, so order them on one stream. A wave that waits longer than 10 s
+ * leaves (the image is then invalid); this call reports no device-side
+ * error. Errors: ASK_EINVAL (arguments, size, form), ASK_EDEVICE (no
+ * current device, or a launch failed). */
+ask_status ask_dwell_subdiv_noalloc(const ask_window *win, const ask_params *params,
+                                    uint32_t *d_out, void *stream);
+
 /* A batch of n >= 1 subdivision images rendered by one sequence of launches
  * over one shared region queue: one seeding pass for all images, then one
  * persistent kernel (or one kernel per level) whose waves take regions of

@@ -104,6 +104,8 @@ SIGNATURES = {
                                        _P]),
     "ask_dwell_subdiv": (C.c_int, [_P, C.POINTER(ask_window), C.POINTER(ask_params), _P, _P,
                                    C.POINTER(ask_stats)]),
+    "ask_dwell_subdiv_noalloc": (C.c_int, [C.POINTER(ask_window), C.POINTER(ask_params), _P,
+                                           _P]),
     "ask_dwell_batch": (C.c_int, [_P, C.c_uint32, C.POINTER(ask_window), C.POINTER(ask_params),
                                   C.c_uint32, C.POINTER(C.c_void_p), _P, C.POINTER(ask_stats)]),
     "ask_synchronize": (C.c_int, [_P, _P]),
@@ -226,6 +228,15 @@ def ask_dwell_subdiv(ctx, win, prm, d_out, stream=0, want_stats=False):
     _check(lib.ask_dwell_subdiv(ctx, C.byref(win), C.byref(prm), _P(d_out), _P(stream),
                                 C.byref(st) if st is not None else None), ctx)
     return st.as_dict() if st is not None else None
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def ask_dwell_subdiv_noalloc(win, prm, d_out, stream=0):
+    """The subdivision image without a context and without allocating (the
+    render works in the library's fixed device array of the current device)."""
+    _check(lib.ask_dwell_subdiv_noalloc(C.byref(win), C.byref(prm), _P(d_out), _P(stream)))
 
 
 def ask_synchronize(ctx, stream=0):

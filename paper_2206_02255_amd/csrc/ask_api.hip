@@ -18,6 +18,8 @@
 
 #include "ask_internal.hpp"
 
+#include <mutex>
+
 using namespace ask;
 
 struct ask_ctx {
@@ -1243,6 +1245,110 @@ ask_status ask_server_destroy(ask_server *sv) {
     delete sv;
     return late ? fail(ctx, ASK_ETIMEOUT, "server requests did not finish in time%s", nullptr)
                 : ASK_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free subdivision (include/ask.h, ask_dwell_subdiv_noalloc): the
+// render's control words and region queue live in one file-scope device
+// array instead of context memory.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kScratchBytes = ASK_NOALLOC_SCRATCH_BYTES;
+constexpr size_t kScratchQueueOffset = 4096;  // the control words come first
+static_assert(kCtrlWords * sizeof(uint32_t) <= kScratchQueueOffset, "control words fit");
+
+// Every device the library runs on holds its own copy of this array, at its
+// own address, until the process ends. Host code never uses its name as an
+// address: each device's address comes from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+
+struct ScratchDevice {
+    std::once_flag once;
+    hipError_t err = hipSuccess;
+    unsigned char *ptr = nullptr;  // this device's address of `scratch`
+    uint32_t grid_persistent = 1;
+    uint32_t resident_level = 1;
+    uint64_t wait_ticks = 0;
+};
+
+ScratchDevice g_scratch[kMaxDevices];
+
+// Once per device, with that device current: the device address of the
+// scratch array, and the launch sizes of the persistent and level kernels.
+void scratch_setup(ScratchDevice &d) {
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    int dev = 0, cus = 0, occ_p = 1, occ_l = 1, khz = 0;
+    if (e == hipSuccess)
+        e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = occupancy_persistent(&occ_p);
+    if (e == hipSuccess)
+        e = occupancy_level(&occ_l);
+    if (e == hipSuccess &&
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess)
+        khz = 0;
+    (void)hipGetLastError();
+    d.err = e;
+    if (e != hipSuccess || !p)
+        return;
+    d.ptr = static_cast<unsigned char *>(p);
+    d.grid_persistent = (uint32_t)(std::max(1, cus) * std::max(1, occ_p));
+    d.resident_level = (uint32_t)(std::max(1, cus) * std::max(1, occ_l));
+    d.wait_ticks = (uint64_t)(10.0 * (khz > 0 ? 1e3 * khz : 1e8));  // 10 s
+}
+
+}  // namespace
+
+extern "C" {
+
+ask_status ask_dwell_subdiv_noalloc(const ask_window *win, const ask_params *params,
+                                    uint32_t *d_out, void *stream) {
+    if (ask_validate(win, params) != ASK_OK || !params || !d_out)
+        return ASK_EINVAL;
+    if (params->form != ASK_FORM_LEVELS && params->form != ASK_FORM_PERSISTENT)
+        return ASK_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        return ASK_EDEVICE;
+    }
+    ScratchDevice &d = g_scratch[dev];
+    std::call_once(d.once, scratch_setup, std::ref(d));
+    if (d.err != hipSuccess || !d.ptr)
+        return ASK_EDEVICE;
+    const Image im = make_image(win, params, d_out);
+    Plan p;
+    if (plan_render(nullptr, &im, 1, params->form, p) != ASK_OK)
+        return ASK_EINVAL;
+    // The worst case must fit: then no queue can overflow.
+    const uint64_t room = (kScratchBytes - kScratchQueueOffset) / sizeof(Region);
+    const uint64_t per_table = params->form == ASK_FORM_PERSISTENT ? room : room / 2;
+    if (p.need > per_table)
+        return ASK_EINVAL;
+    Buffers bf;
+    bf.ctrl = reinterpret_cast<uint32_t *>(d.ptr);
+    Region *q = reinterpret_cast<Region *>(d.ptr + kScratchQueueOffset);
+    bf.queue = q;
+    bf.lvq[0] = q;
+    bf.lvq[1] = q + per_table;
+    // The persistent queue is cleared (by a kernel) before every render and
+    // its entries carry one fixed tag, so no entry of an earlier call is
+    // ever taken; only the entries this render can reach are cleared.
+    bf.cap = params->form == ASK_FORM_PERSISTENT ? p.need : per_table;
+    bf.clear_queue = params->form == ASK_FORM_PERSISTENT;
+    bf.epoch = 1;
+    bf.wait_ticks = d.wait_ticks;
+    bf.grid_persistent = d.grid_persistent;
+    bf.resident_level = d.resident_level;
+    return launch_render(nullptr, p, bf, &im, 1, params->form, (hipStream_t)stream);
 }
 
 }  // extern "C"
