@@ -133,7 +133,7 @@ def test_deep_zoom_blocks(env, ref):
     win = ask.window(w)
     params = [workloads.DEEP_PARAMS]
     hit = autotune.lookup(autotune.workload_key(win, "persistent"))
-    if hit and "tile" in hit and (hit["g"], hit["r"], hit["B"]) != tuple(params[0]):
+    if hit and "tile" in hit and Params(hit["g"], hit["r"], hit["B"]) != params[0]:
         params.append(Params(hit["g"], hit["r"], hit["B"]))
     rng = np.random.default_rng(33)
     px, py = _blocks(rng, w.W, w.H, 12, 32)
