@@ -58,33 +58,122 @@ __device__ __forceinline__ double axis_point(double centre, double half, uint32_
     return centre + t;
 }
 
-// q <- q^2 + c with q = a + b i + e j, c = cr + ci i: the first k with
-// |q_k|^2 > 4, else D. b^2 + e^2 is summed first, so e = 0 performs the
-// complex iteration's operations exactly.
-__device__ __forceinline__ uint32_t quat_dwell(double a, double b, double e, double cr,
-                                               double ci, uint32_t D) {
-    for (uint32_t k = 1; k <= D; ++k) {
-        const double a2 = a * a, b2 = b * b, e2 = e * e;
-        const double ab = a * b, ae = a * e;
-        a = (a2 - (b2 + e2)) + cr;
-        b = (ab + ab) + ci;
-        e = (ae + ae) + 0.0;
-        const double mag = a * a + (b * b + e * e);
-        if (mag > 4.0)
-            return k;
-    }
-    return D;
-}
-
-__device__ __forceinline__ uint32_t voxel_dwell(const Vol3 &v, uint32_t x, uint32_t y,
-                                                uint32_t z) {
-    return quat_dwell(axis_point(v.cx, v.hx, x, v.n[0]), axis_point(v.cy, v.hy, y, v.n[1]),
-                      axis_point(v.cz, v.hz, z, v.n[2]), v.cr, v.ci, v.D);
-}
-
 __device__ __forceinline__ void put_voxel(const Vol3 &v, uint32_t x, uint32_t y, uint32_t z,
                                           uint32_t d) {
     v.out[((uint64_t)z * v.n[1] + y) * v.n[0] + x] = d;
+}
+
+// ---------------------------------------------------------------------------
+// Voxel streams with lane refill. Voxels near the set's boundary have dwells
+// that differ by orders of magnitude from their neighbours', so a wave that
+// gives each lane one voxel waits for its slowest voxel with most lanes
+// idle. Here every lane iterates its own voxel, testing for escape after
+// every iteration, and every kRound3 iterations the lanes whose voxel has
+// finished take the next voxels of the stream.
+//
+// The dwell: q <- q^2 + c with q = a + b i + e j, c = cr + ci i, the first k
+// with |q_k|^2 > 4, else D; per step a' = (a^2 - (b^2 + e^2)) + cr,
+// b' = (ab + ab) + ci, e' = (ae + ae) + 0, |q'|^2 = a'^2 + (b'^2 + e'^2),
+// every operation rounded on its own. b^2 + e^2 is summed first, so e = 0
+// performs the complex iteration's operations exactly, and it is kept for
+// the next step. The "+ 0" of e's update is left out: it can only turn a -0
+// into a +0, and e enters a, b and |q|^2 only through e^2 (and, as a
+// factor, e's own update), so no dwell changes.
+//
+// voxel_of(i, x, y, z) names voxel i of the stream (false: none there);
+// done(x, y, z, dwell, surface) is called by the lane that finished a voxel,
+// surface telling whether it was one of the first n_surf stream positions.
+// A surface stream (kSurface) takes positions [0, n_surf) first and decides
+// whether their dwells are all equal as it goes: once some voxel has
+// finished with dwell v (the least of the first round in which any
+// finished), another finishing with a different dwell, or one still running
+// after v iterations, shows the surface is mixed. It then stops (n_all ==
+// n_surf), or (n_all > n_surf: a leaf box) goes on with the surface's other
+// positions and then positions [n_surf, n_all), the box's inside. Returns
+// 0 for a uniform surface (dwell v), 1 for a mixed one that stopped, 2 for a
+// mixed one whose leaf was completed (and 2 for plain streams).
+// ---------------------------------------------------------------------------
+constexpr uint32_t kRound3 = 8;
+
+template <bool kSurface, class VoxelOf, class Done>
+__device__ __forceinline__ uint32_t quat_stream(const Vol3 &v, uint32_t n_surf, uint32_t n_all,
+                                                VoxelOf voxel_of, Done done, uint32_t &val) {
+    const uint32_t D = v.D;
+    const double cr = v.cr, ci = v.ci;
+    uint32_t next = 0;
+    uint32_t n = kSurface ? n_surf : n_all;
+    bool scanning = kSurface;
+    bool have = false, vset = false, surf = false;
+    uint32_t x = 0, y = 0, z = 0, k = 0;
+    double a = 0.0, b = 0.0, e = 0.0, a2 = 0.0, s2 = 0.0;
+    for (;;) {
+        unsigned long long idle = __ballot(!have);
+        while (idle && next < n) {
+            if (!have) {
+                const uint32_t j = next + (uint32_t)__builtin_amdgcn_mbcnt_hi(
+                                              (uint32_t)(idle >> 32),
+                                              __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
+                if (j < n && voxel_of(j, x, y, z)) {
+                    have = true;
+                    surf = kSurface && j < n_surf;
+                    a = axis_point(v.cx, v.hx, x, v.n[0]);
+                    b = axis_point(v.cy, v.hy, y, v.n[1]);
+                    e = axis_point(v.cz, v.hz, z, v.n[2]);
+                    a2 = a * a;
+                    s2 = b * b + e * e;
+                    k = 0;
+                }
+            }
+            next = min(n, next + (uint32_t)__popcll(idle));
+            idle = __ballot(!have);
+        }
+        if (__ballot(have) == 0)
+            break;
+        uint32_t dw = 0;
+        bool fin = false;
+        if (have) {
+            for (uint32_t u = 0; u < kRound3; ++u) {
+                ++k;
+                const double ab = a * b, ae = a * e;
+                a = (a2 - s2) + cr;
+                b = (ab + ab) + ci;
+                e = ae + ae;
+                a2 = a * a;
+                s2 = b * b + e * e;
+                if (a2 + s2 > 4.0) {
+                    dw = k;
+                    fin = true;
+                    break;
+                }
+                if (k >= D) {
+                    dw = D;
+                    fin = true;
+                    break;
+                }
+            }
+            if (fin) {
+                done(x, y, z, dw, surf);
+                have = false;
+            }
+        }
+        if (kSurface && scanning) {
+            if (!vset && __ballot(fin)) {
+                uint32_t m = fin ? dw : 0xffffffffu;
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1)
+                    m = min(m, (uint32_t)__shfl_xor((unsigned int)m, o));
+                val = __builtin_amdgcn_readfirstlane(m);
+                vset = true;
+            }
+            if (vset && __ballot((fin && dw != val) || (have && k >= val))) {
+                if (n_all == n_surf)
+                    return 1;
+                scanning = false;
+                n = n_all;
+            }
+        }
+    }
+    return (kSurface && scanning) ? 0u : 2u;
 }
 
 // ---------------------------------------------------------------------------
@@ -147,23 +236,35 @@ __device__ __forceinline__ bool cell_box(const Vol3 &v, uint64_t G, const uint32
     return ok;
 }
 
-__device__ __forceinline__ uint64_t wave_base(unsigned long long *counter, uint64_t mask,
-                                              uint32_t lane) {
-    uint64_t base = 0;
-    if (lane == 0 && mask)
-        base = atomicAdd(counter, (unsigned long long)__popcll(mask));
-    const uint32_t lo = __shfl((uint32_t)base, 0), hi = __shfl((uint32_t)(base >> 32), 0);
-    return (uint64_t)hi << 32 | lo;
+// Wave-wide values come from the first active lane through readfirstlane,
+// which reads that lane whatever branch the optimiser puts the atomic in.
+__device__ __forceinline__ bool first_lane3() {
+    const uint32_t lane = __lane_id();
+    return lane == __builtin_amdgcn_readfirstlane(lane);
 }
 
-// Lane 0 adds n to the counter; every lane gets the counter's old value.
-__device__ __forceinline__ uint64_t wave_claim(unsigned long long *counter, uint64_t n,
-                                               uint32_t lane) {
+__device__ __forceinline__ uint64_t uniform64_3(uint64_t x) {
+    return (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(x >> 32)) << 32 |
+           __builtin_amdgcn_readfirstlane((uint32_t)x);
+}
+
+// One atomic add of the wave's count of set mask bits; every lane gets the
+// counter's old value.
+__device__ __forceinline__ uint64_t wave_base(unsigned long long *counter, uint64_t mask,
+                                              uint32_t) {
     uint64_t base = 0;
-    if (lane == 0)
+    if (mask && first_lane3())
+        base = atomicAdd(counter, (unsigned long long)__popcll(mask));
+    return uniform64_3(base);
+}
+
+// One atomic add of n; every lane gets the counter's old value.
+__device__ __forceinline__ uint64_t wave_claim(unsigned long long *counter, uint64_t n,
+                                               uint32_t) {
+    uint64_t base = 0;
+    if (first_lane3())
         base = atomicAdd(counter, (unsigned long long)n);
-    const uint32_t lo = __shfl((uint32_t)base, 0), hi = __shfl((uint32_t)(base >> 32), 0);
-    return (uint64_t)hi << 32 | lo;
+    return uniform64_3(base);
 }
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask, uint32_t lane) {
@@ -174,18 +275,30 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask, uint32_t lane) {
 // Kernels
 // ---------------------------------------------------------------------------
 
-// Every voxel: a workgroup owns a 16 x 16 tile of one z slice.
+// Every voxel: each wave streams the voxels of one kTile3 x kTile3 tile of a
+// z slice (row by row, lane refilled), four waves per workgroup.
+constexpr uint32_t kTile3 = 32;
+
 __global__ __launch_bounds__(kThreads) void exhaustive3_kernel(Vol3 v, uint32_t tiles_x,
-                                                               uint32_t tiles_y) {
-    uint32_t b = blockIdx.x;
-    const uint32_t bx = b % tiles_x;
-    b /= tiles_x;
-    const uint32_t by = b % tiles_y;
-    const uint32_t z = b / tiles_y;
-    const uint32_t x = bx * 16 + (threadIdx.x & 15);
-    const uint32_t y = by * 16 + (threadIdx.x >> 4);
-    if (x < v.n[0] && y < v.n[1] && z < v.n[2])
-        put_voxel(v, x, y, z, voxel_dwell(v, x, y, z));
+                                                               uint32_t tiles_y, uint64_t tiles) {
+    const uint64_t t = (uint64_t)blockIdx.x * kWavesPer + threadIdx.x / kLanes;
+    if (t >= tiles)
+        return;
+    const uint32_t bx = (uint32_t)(t % tiles_x);
+    const uint32_t by = (uint32_t)((t / tiles_x) % tiles_y);
+    const uint32_t z = (uint32_t)(t / ((uint64_t)tiles_x * tiles_y));
+    const uint32_t x0 = bx * kTile3, y0 = by * kTile3;
+    uint32_t val = 0;
+    quat_stream<false>(
+        v, 0u, kTile3 * kTile3,
+        [&](uint32_t i, uint32_t &x, uint32_t &y, uint32_t &zz) {
+            x = x0 + i % kTile3;
+            y = y0 + i / kTile3;
+            zz = z;
+            return x < v.n[0] && y < v.n[1];
+        },
+        [&](uint32_t x, uint32_t y, uint32_t zz, uint32_t d, bool) { put_voxel(v, x, y, zz, d); },
+        val);
 }
 
 __global__ __launch_bounds__(kThreads) void reset3_kernel(unsigned long long *ctrl) {
@@ -288,51 +401,50 @@ __global__ __launch_bounds__(kThreads) void level3_kernel(Vol3 v, Level3 L) {
                 continue;
             }
             const uint32_t w = hi[0] - lo[0], h = hi[1] - lo[1], l = hi[2] - lo[2];
-            const uint32_t first = voxel_dwell(v, lo[0], lo[1], lo[2]);
             const uint32_t S = surface_count(w, h, l);
             const bool leaf_size = w <= L.B && h <= L.B && l <= L.B;
-            // The scan writes every surface dwell it computes, so a leaf box only
-            // finishes the surface from where the scan stopped and adds its interior.
-            bool uniform = true;
-            uint32_t t0 = 0;
-            for (; t0 < S; t0 += kLanes) {
-                const uint32_t t = t0 + lane;
-                bool differs = false;
-                if (t < S) {
-                    uint32_t x, y, z;
+            // The surface in a spread order (64 arcs, offsets within an arc
+            // in bit-reversed round order, as for 2-D rings), so a mixed
+            // surface shows it early; a leaf box's stream goes on into its
+            // inside. Every finished surface dwell is written: whatever
+            // follows, a voxel on a scanned surface ends with its own dwell.
+            const uint32_t q = (S + kLanes - 1) / kLanes;
+            const uint32_t bits = q > 1 ? 32u - (uint32_t)__builtin_clz(q - 1) : 0u;
+            const uint32_t n_surf = kLanes << bits;
+            const uint32_t iw = w > 2 ? w - 2 : 0, ih = h > 2 ? h - 2 : 0, il = l > 2 ? l - 2 : 0;
+            const uint32_t iwh = iw * ih, inside = (w <= 2 || h <= 2 || l <= 2) ? 0u : iwh * il;
+            uint32_t first = 0;
+            const uint32_t outcome = quat_stream<true>(
+                v, n_surf, leaf_size ? n_surf + inside + 1u : n_surf,
+                [&](uint32_t j, uint32_t &x, uint32_t &y, uint32_t &z) {
+                    if (j >= n_surf) {
+                        const uint32_t t = j - n_surf;
+                        if (t >= inside)
+                            return false;
+                        x = lo[0] + 1 + t % iw;
+                        y = lo[1] + 1 + (t / iw) % ih;
+                        z = lo[2] + 1 + t / iwh;
+                        return true;
+                    }
+                    const uint32_t round = j / kLanes;
+                    const uint32_t off = bits ? __brev(round) >> (32u - bits) : 0u;
+                    const uint32_t t = (j % kLanes) * q + off;
+                    if (off >= q || t >= S)
+                        return false;
                     surface_voxel(t, w, h, l, x, y, z);
-                    const uint32_t d = voxel_dwell(v, lo[0] + x, lo[1] + y, lo[2] + z);
-                    if (leaf_size)
-                        put_voxel(v, lo[0] + x, lo[1] + y, lo[2] + z, d);
-                    differs = d != first;
-                }
-                if (__ballot(differs)) {
-                    uniform = false;
-                    t0 += kLanes;
-                    break;
-                }
-            }
+                    x += lo[0];
+                    y += lo[1];
+                    z += lo[2];
+                    return true;
+                },
+                [&](uint32_t x, uint32_t y, uint32_t z, uint32_t d, bool) { put_voxel(v, x, y, z, d); },
+                first);
             const uint32_t wh = w * h, n = wh * l;
-            if (uniform) {
+            if (outcome == 0) {
                 for (uint32_t t = lane; t < n; t += kLanes)
                     put_voxel(v, lo[0] + t % w, lo[1] + (t / w) % h, lo[2] + t / wh, first);
                 ++nfill;
             } else if (leaf_size) {
-                for (uint32_t t = t0 + lane; t < S; t += kLanes) {
-                    uint32_t x, y, z;
-                    surface_voxel(t, w, h, l, x, y, z);
-                    put_voxel(v, lo[0] + x, lo[1] + y, lo[2] + z,
-                              voxel_dwell(v, lo[0] + x, lo[1] + y, lo[2] + z));
-                }
-                // interior: (w - 2) x (h - 2) x (l - 2), empty when the box is all surface
-                const uint32_t iw = w > 2 ? w - 2 : 0, ih = h > 2 ? h - 2 : 0,
-                               il = l > 2 ? l - 2 : 0;
-                const uint32_t iwh = iw * ih, in = iwh * il;
-                for (uint32_t t = lane; t < in; t += kLanes) {
-                    const uint32_t x = lo[0] + 1 + t % iw, y = lo[1] + 1 + (t / iw) % ih,
-                                   z = lo[2] + 1 + t / iwh;
-                    put_voxel(v, x, y, z, voxel_dwell(v, x, y, z));
-                }
                 ++nleaf;
             } else {
                 const uint32_t r = L.r, kids = r * r * r;
@@ -464,12 +576,13 @@ extern "C" ask_status ask3_workspace_bytes(const ask_volume *v, const ask3_param
 extern "C" ask_status ask3_dwell_exhaustive(const ask_volume *v, uint32_t *d_out, void *stream) {
     if (!volume_ok(v) || !d_out)
         return ASK_EINVAL;
-    const uint32_t tx = (v->W + 15) / 16, ty = (v->H + 15) / 16;
-    const uint64_t blocks = (uint64_t)tx * ty * v->L;
+    const uint32_t tx = (v->W + kTile3 - 1) / kTile3, ty = (v->H + kTile3 - 1) / kTile3;
+    const uint64_t tiles = (uint64_t)tx * ty * v->L;
+    const uint64_t blocks = (tiles + kWavesPer - 1) / kWavesPer;
     if (blocks >= (1ull << 31))
         return ASK_EINVAL;
     hipLaunchKernelGGL(exhaustive3_kernel, dim3((uint32_t)blocks), dim3(kThreads), 0,
-                       (hipStream_t)stream, make_vol(v, d_out), tx, ty);
+                       (hipStream_t)stream, make_vol(v, d_out), tx, ty, tiles);
     return launched();
 }
 

@@ -24,6 +24,10 @@ VOLUMES = [
     (Volume(-1.6, 1.6, -0.01, 0.01, -0.01, 0.01, 57, 1, 1, 100, c=(-1.0, 0.0)), 3, 2, 2),
     (Volume(-1.6, 1.6, -1.2, 1.2, -0.01, 0.01, 90, 70, 1, 200, c=(-0.2, 0.6)), 4, 2, 4),
     (Volume(-1.0, 1.0, -1.0, 1.0, -1.0, 1.0, 3, 5, 2, 60, c=(-0.2, 0.6)), 8, 2, 1),
+    # long orbits: many refill rounds per voxel, surfaces at D
+    (Volume(-1.4, 1.4, -1.3, 1.3, -0.7, 0.7, 70, 66, 35, 3000, c=(-0.125, 0.65)), 4, 2, 5),
+    # c beyond |c| = 2: every orbit escapes at once or never starts close
+    (Volume(-2.5, 2.5, -2.5, 2.5, -2.5, 2.5, 33, 30, 27, 100, c=(2.1, 0.3)), 3, 2, 4),
 ]
 
 
