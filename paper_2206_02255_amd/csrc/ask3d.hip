@@ -53,7 +53,7 @@ struct Level3 {
 };
 
 __device__ __forceinline__ double axis_point(double centre, double half, uint32_t p, uint32_t n) {
-    const int64_t k = 2 * (int64_t)p + 1 - (int64_t)n;
+    const int k = 2 * (int)p + 1 - (int)n;  // odd, |k| < 2^17: exact as int and as double
     const double t = (double)k * half;
     return centre + t;
 }
@@ -67,9 +67,9 @@ __device__ __forceinline__ void put_voxel(const Vol3 &v, uint32_t x, uint32_t y,
 // Voxel streams with lane refill. Voxels near the set's boundary have dwells
 // that differ by orders of magnitude from their neighbours', so a wave that
 // gives each lane one voxel waits for its slowest voxel with most lanes
-// idle. Here every lane iterates its own voxel, testing for escape after
-// every iteration, and every kRound3 iterations the lanes whose voxel has
-// finished take the next voxels of the stream.
+// idle. Here every lane iterates its own voxel, and after every stretch of
+// kStride3 iterations the lanes whose voxel has finished take the next
+// voxels of the stream.
 //
 // The dwell: q <- q^2 + c with q = a + b i + e j, c = cr + ci i, the first k
 // with |q_k|^2 > 4, else D; per step a' = (a^2 - (b^2 + e^2)) + cr,
@@ -80,12 +80,23 @@ __device__ __forceinline__ void put_voxel(const Vol3 &v, uint32_t x, uint32_t y,
 // into a +0, and e enters a, b and |q|^2 only through e^2 (and, as a
 // factor, e's own update), so no dwell changes.
 //
+// A stretch runs without testing and then tests !(|q|^2 <= 4), which also
+// catches inf and NaN. The quaternion norm is multiplicative, so
+// |q'| >= |q|^2 - |c|: when |c|^2 <= 3.99, an orbit that once has
+// |q|^2 > 4 grows at every later step (2 - |c| is far above the rounding),
+// and a passing test proves that no escape happened inside the stretch. A
+// failing test replays the stretch from its saved start, testing every
+// step, which finds the same first k as a test after every iteration.
+// Volumes with |c|^2 > 3.99 test after every iteration throughout.
+// Iterations past D are harmless: an escape after D, or none by D, both
+// give D.
+//
 // voxel_of(i, x, y, z) names voxel i of the stream (false: none there);
 // done(x, y, z, dwell, surface) is called by the lane that finished a voxel,
 // surface telling whether it was one of the first n_surf stream positions.
 // A surface stream (kSurface) takes positions [0, n_surf) first and decides
 // whether their dwells are all equal as it goes: once some voxel has
-// finished with dwell v (the least of the first round in which any
+// finished with dwell v (the least of the first stretch in which any
 // finished), another finishing with a different dwell, or one still running
 // after v iterations, shows the surface is mixed. It then stops (n_all ==
 // n_surf), or (n_all > n_surf: a leaf box) goes on with the surface's other
@@ -93,13 +104,25 @@ __device__ __forceinline__ void put_voxel(const Vol3 &v, uint32_t x, uint32_t y,
 // 0 for a uniform surface (dwell v), 1 for a mixed one that stopped, 2 for a
 // mixed one whose leaf was completed (and 2 for plain streams).
 // ---------------------------------------------------------------------------
-constexpr uint32_t kRound3 = 8;
+constexpr uint32_t kStride3 = 8;
+
+// One step of the orbit; s2 = b^2 + e^2 of the new q.
+__device__ __forceinline__ void quat_step(double &a, double &b, double &e, double &a2, double &s2,
+                                          double cr, double ci) {
+    const double ab = a * b, ae = a * e;
+    a = (a2 - s2) + cr;
+    b = (ab + ab) + ci;
+    e = ae + ae;
+    a2 = a * a;
+    s2 = b * b + e * e;
+}
 
 template <bool kSurface, class VoxelOf, class Done>
 __device__ __forceinline__ uint32_t quat_stream(const Vol3 &v, uint32_t n_surf, uint32_t n_all,
                                                 VoxelOf voxel_of, Done done, uint32_t &val) {
     const uint32_t D = v.D;
     const double cr = v.cr, ci = v.ci;
+    const bool special = !(cr * cr + ci * ci <= 3.99);  // the same for every voxel
     uint32_t next = 0;
     uint32_t n = kSurface ? n_surf : n_all;
     bool scanning = kSurface;
@@ -132,26 +155,51 @@ __device__ __forceinline__ uint32_t quat_stream(const Vol3 &v, uint32_t n_surf, 
         uint32_t dw = 0;
         bool fin = false;
         if (have) {
-            for (uint32_t u = 0; u < kRound3; ++u) {
-                ++k;
-                const double ab = a * b, ae = a * e;
-                a = (a2 - s2) + cr;
-                b = (ab + ab) + ci;
-                e = ae + ae;
-                a2 = a * a;
-                s2 = b * b + e * e;
-                if (a2 + s2 > 4.0) {
-                    dw = k;
-                    fin = true;
-                    break;
+            bool replay = false;
+            if (__builtin_expect(!special, 1)) {
+                const double sa = a, sb = b, se = e, sa2 = a2, ss2 = s2;
+#pragma unroll
+                for (uint32_t u = 0; u < kStride3; ++u)
+                    quat_step(a, b, e, a2, s2, cr, ci);
+                if (!(a2 + s2 <= 4.0)) {
+                    // Escapes are rare: an empty asm keeps the restore on a
+                    // branch, so the common stretch pays no select per
+                    // register of the state.
+                    asm volatile("");
+                    a = sa, b = sb, e = se, a2 = sa2, s2 = ss2;
+                    replay = true;
+                } else {
+                    k += kStride3;
                 }
-                if (k >= D) {
-                    dw = D;
-                    fin = true;
-                    break;
+            } else {
+                for (uint32_t u = 0; u < kStride3; ++u) {
+                    quat_step(a, b, e, a2, s2, cr, ci);
+                    if (a2 + s2 > 4.0) {
+                        dw = k + u + 1;
+                        fin = true;
+                        break;
+                    }
                 }
+                if (!fin)
+                    k += kStride3;
+            }
+            if (replay) {
+                // the stretch again with a test after every step
+                while (k < D) {
+                    ++k;
+                    quat_step(a, b, e, a2, s2, cr, ci);
+                    if (a2 + s2 > 4.0)
+                        break;
+                }
+                dw = k;
+                fin = true;
+            }
+            if (!fin && k >= D) {
+                dw = D;
+                fin = true;
             }
             if (fin) {
+                dw = dw > D ? D : dw;
                 done(x, y, z, dw, surf);
                 have = false;
             }
@@ -394,7 +442,7 @@ __global__ __launch_bounds__(kThreads) void level3_kernel(Vol3 v, Level3 L) {
         const uint64_t e1 = std::min(e0 + chunk, count);
         for (uint64_t e = e0; e < e1; ++e) {
             uint32_t p[3], lo[3], hi[3];
-            scalar_cell(L.in[e], L.G, L.curve, p);
+            scalar_cell(uniform64_3(L.in[e]), L.G, L.curve, p);  // wave-uniform box
             if (!cell_box(v, L.G, p, lo, hi)) {
                 if (lane == 0)
                     atomicOr(&L.ctrl[kOverW], 2ull);
