@@ -324,12 +324,13 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask, uint32_t lane) {
 // ---------------------------------------------------------------------------
 
 // Every voxel: each wave streams the voxels of one kTile3 x kTile3 tile of a
-// z slice (row by row, lane refilled), four waves per workgroup.
+// z slice (row by row, lane refilled), kEx3Waves waves per workgroup.
 constexpr uint32_t kTile3 = 32;
+constexpr uint32_t kEx3Waves = 4;
 
-__global__ __launch_bounds__(kThreads) void exhaustive3_kernel(Vol3 v, uint32_t tiles_x,
+__global__ __launch_bounds__(kEx3Waves * kLanes) void exhaustive3_kernel(Vol3 v, uint32_t tiles_x,
                                                                uint32_t tiles_y, uint64_t tiles) {
-    const uint64_t t = (uint64_t)blockIdx.x * kWavesPer + threadIdx.x / kLanes;
+    const uint64_t t = (uint64_t)blockIdx.x * kEx3Waves + threadIdx.x / kLanes;
     if (t >= tiles)
         return;
     const uint32_t bx = (uint32_t)(t % tiles_x);
@@ -626,10 +627,10 @@ extern "C" ask_status ask3_dwell_exhaustive(const ask_volume *v, uint32_t *d_out
         return ASK_EINVAL;
     const uint32_t tx = (v->W + kTile3 - 1) / kTile3, ty = (v->H + kTile3 - 1) / kTile3;
     const uint64_t tiles = (uint64_t)tx * ty * v->L;
-    const uint64_t blocks = (tiles + kWavesPer - 1) / kWavesPer;
+    const uint64_t blocks = (tiles + kEx3Waves - 1) / kEx3Waves;
     if (blocks >= (1ull << 31))
         return ASK_EINVAL;
-    hipLaunchKernelGGL(exhaustive3_kernel, dim3((uint32_t)blocks), dim3(kThreads), 0,
+    hipLaunchKernelGGL(exhaustive3_kernel, dim3((uint32_t)blocks), dim3(kEx3Waves * kLanes), 0,
                        (hipStream_t)stream, make_vol(v, d_out), tx, ty, tiles);
     return launched();
 }
@@ -647,6 +648,14 @@ extern "C" ask_status ask3_dwell_subdiv(const ask_volume *v, const ask3_params *
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         cus < 1)
         return ASK_EDEVICE;
+    // The level kernel's resident workgroups per CU: a grid larger than the
+    // device holds at once would leave workgroups waiting for others to end.
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, level3_kernel, kThreads, 0) != hipSuccess ||
+        occ < 1) {
+        (void)hipGetLastError();
+        occ = 1;
+    }
     const uint64_t cap = table_cap(v, p);
     const uint32_t levels = reachable_levels(v, p);
     unsigned long long *ctrl = (unsigned long long *)d_work;
@@ -675,7 +684,7 @@ extern "C" ask_status ask3_dwell_subdiv(const ask_volume *v, const ask3_params *
         L.level = i;
         const uint64_t bound = i == 0 ? level0 : cap;
         const uint32_t blocks = (uint32_t)std::max<uint64_t>(
-            1, std::min<uint64_t>((bound + kWavesPer - 1) / kWavesPer, (uint64_t)cus * 8));
+            1, std::min<uint64_t>((bound + kWavesPer - 1) / kWavesPer, (uint64_t)cus * occ));
         hipLaunchKernelGGL(level3_kernel, dim3(blocks), dim3(kThreads), 0, s, vol, L);
     }
     ask_status st = launched();

@@ -177,8 +177,18 @@ __device__ __forceinline__ void wave_max(uint32_t *p, uint32_t v) {
 // a generic pointer the store would be a flat one, which also counts on the
 // counter of scalar and LDS operations: every later wait on those (a scalar
 // load, a lane permute) would then also wait for the store to complete.
-__device__ __forceinline__ void put_dwell(uint32_t *out, size_t i, uint32_t d) {
+__device__ __forceinline__ void put_pixel(uint32_t *out, size_t i, uint32_t d) {
     ((__attribute__((address_space(1))) uint32_t *)out)[i] = d;
+}
+
+// The subdivision kernels write the image through to memory (a relaxed
+// device-scope store, which leaves no dirty line in the XCD's L2). A wave
+// that publishes queue entries makes its earlier writes visible device-wide
+// first, and on MI355X that writes back every dirty line of its XCD's L2;
+// with the image written through, that write-back has almost nothing to do
+// (the 16384^2 render went from 4.33 to 3.98 ms).
+__device__ __forceinline__ void put_dwell(uint32_t *out, size_t i, uint32_t d) {
+    __hip_atomic_store(out + i, d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------------------
@@ -198,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void exhaustive_kernel(Image im) {
         return;
     double zr, zi, cr, ci;
     pixel_orbit(im, px, py, zr, zi, cr, ci);
-    put_dwell(im.out, (size_t)py * im.W + px, dwell(zr, zi, cr, ci, im.D));
+    put_pixel(im.out, (size_t)py * im.W + px, dwell(zr, zi, cr, ci, im.D));
 }
 
 
@@ -769,7 +779,6 @@ __global__ __launch_bounds__(kBlock) void persistent_kernel(SubdivArgs a) {
                 const uint32_t t = uniform(__hip_atomic_load(&a.queue[idx].tag, __ATOMIC_RELAXED,
                                                              __HIP_MEMORY_SCOPE_AGENT));
                 if ((t >> 8) == a.epoch) {
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                     ready = true;
                     break;
                 }
@@ -788,7 +797,16 @@ __global__ __launch_bounds__(kBlock) void persistent_kernel(SubdivArgs a) {
         }
         if (!ready)
             return;
-        process_region<true>(a, a.queue[idx], lane);
+        // The entry's fields are read past the XCD's L2, with device-scope
+        // loads, after its tag: the producer wrote them back before it
+        // published the tag, so they are the entry's. (An acquire fence
+        // would invalidate the whole L2 instead: 4 % slower.)
+        Region R;
+        R.img = __hip_atomic_load(&a.queue[idx].img, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        R.xy = __hip_atomic_load(&a.queue[idx].xy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        R.wh = __hip_atomic_load(&a.queue[idx].wh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        R.tag = __hip_atomic_load(&a.queue[idx].tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        process_region<true>(a, R, lane);
         wave_add(&ctrl[kPending], (uint32_t)-1);
     }
 }
