@@ -240,6 +240,24 @@ static void put(const vol *v, uint32_t *out, uint32_t x, uint32_t y, uint32_t z,
     out[((uint64_t)z * v->n[1] + y) * v->n[0] + x] = d;
 }
 
+/* The sum of the dwells on the box's surface (what a full surface query
+ * computes), and of the voxels inside it. */
+static void box_work(const vol *v, const box3 *b, uint64_t *surface, uint64_t *inside)
+{
+    uint64_t s = 0, in = 0;
+    for (uint32_t z = b->lo[2]; z < b->hi[2]; ++z)
+        for (uint32_t y = b->lo[1]; y < b->hi[1]; ++y)
+            for (uint32_t x = b->lo[0]; x < b->hi[0]; ++x) {
+                uint32_t d = voxel_dwell(v, x, y, z);
+                if (on_surface(b, x, y, z))
+                    s += d;
+                else
+                    in += d;
+            }
+    *surface = s;
+    *inside = in;
+}
+
 /* Decide one box: the dwells on its surface all equal -> fill the box with
  * that dwell; otherwise every side <= B -> compute every voxel; otherwise
  * split it into its r^3 child cells (the empty ones dropped). Returns the
@@ -281,6 +299,7 @@ typedef struct sd_job {
     int order;
     uint32_t B;
     uint8_t *kind;
+    uint64_t *work;  /* per box: surface iterations, and leaf inside iterations */
     pthread_mutex_t mu;
 } sd_job;
 
@@ -298,6 +317,12 @@ static void *sd_worker(void *p)
         decode(j->order, j->G, j->olt[i], c);
         cell_box(j->v, j->G, c, &b);
         j->kind[i] = (uint8_t)decide(j->v, &b, j->B, j->out);
+        if (j->work) {
+            uint64_t surface, inside;
+            box_work(j->v, &b, &surface, &inside);
+            j->work[2 * i] = surface;
+            j->work[2 * i + 1] = j->kind[i] == 2 ? inside : 0;
+        }
     }
 }
 
@@ -339,7 +364,8 @@ int64_t askref3_subdiv(const double box[6], uint32_t W, uint32_t H, uint32_t L,
         uint32_t lv = st->levels++;
         st->regions[lv] = n;
         uint8_t *kind = calloc(n, 1);
-        sd_job j = {&v, out, olt, n, 0, G, order, B, kind, PTHREAD_MUTEX_INITIALIZER};
+        uint64_t *work = calloc(2 * n, sizeof *work);
+        sd_job j = {&v, out, olt, n, 0, G, order, B, kind, work, PTHREAD_MUTEX_INITIALIZER};
         pthread_t th[64];
         for (int t = 0; t < nt; ++t)
             pthread_create(&th[t], NULL, sd_worker, &j);
@@ -349,6 +375,8 @@ int64_t askref3_subdiv(const double box[6], uint32_t W, uint32_t H, uint32_t L,
         uint64_t G1 = G * r, n1 = 0, cap1 = 0;
         uint64_t *olt1 = NULL;
         for (uint64_t i = 0; i < n; ++i) {
+            st->iters_surface += work[2 * i];
+            st->iters_leaf += work[2 * i + 1];
             if (kind[i] == 1)
                 st->fills[lv]++;
             else if (kind[i] == 2)
@@ -373,6 +401,7 @@ int64_t askref3_subdiv(const double box[6], uint32_t W, uint32_t H, uint32_t L,
                     }
         }
         free(kind);
+        free(work);
         free(olt);
         olt = olt1, n = n1, G = G1;
     }

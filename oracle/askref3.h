@@ -15,6 +15,9 @@ typedef struct askref3_stats {
     uint64_t fills[ASKREF3_MAX_LEVELS];
     uint64_t splits[ASKREF3_MAX_LEVELS];
     uint64_t leaves[ASKREF3_MAX_LEVELS];
+    /* The algorithm's work in dwell iterations: the dwells of every scanned
+     * box's whole surface, and of the voxels inside its leaf boxes. */
+    uint64_t iters_surface, iters_leaf;
 } askref3_stats;
 
 /* box = {x0, x1, y0, y1, z0, z1}; m = {cx, cy, cz, hx, hy, hz}. */

@@ -22,11 +22,12 @@ class Stats(C.Structure):
                 ("regions", C.c_uint64 * MAX_LEVELS),
                 ("fills", C.c_uint64 * MAX_LEVELS),
                 ("splits", C.c_uint64 * MAX_LEVELS),
-                ("leaves", C.c_uint64 * MAX_LEVELS)]
+                ("leaves", C.c_uint64 * MAX_LEVELS),
+                ("iters_surface", C.c_uint64), ("iters_leaf", C.c_uint64)]
 
     def as_dict(self):
         n = self.levels
-        d = {"levels": n}
+        d = {"levels": n, "iters_surface": self.iters_surface, "iters_leaf": self.iters_leaf}
         for k in ("regions", "fills", "splits", "leaves"):
             d[k] = list(getattr(self, k)[:n])
         return d

@@ -260,7 +260,8 @@ def brute_subdiv(E, g, r, B):
     L_, H_, W_ = E.shape
     n = (W_, H_, L_)
     S = np.zeros_like(E)
-    stats = {"regions": [], "fills": [], "splits": [], "leaves": []}
+    stats = {"regions": [], "fills": [], "splits": [], "leaves": [],
+             "iters_surface": 0, "iters_leaf": 0}
 
     def span(j, G, m):
         return (j * m) // G, ((j + 1) * m) // G
@@ -280,11 +281,15 @@ def brute_subdiv(E, g, r, B):
             surf = np.ones(blk.shape, bool)
             surf[1:-1, 1:-1, 1:-1] = False
             vals = blk[surf]
+            # the work counters: every decided box's whole surface, and the
+            # inside of every leaf box
+            stats["iters_surface"] += int(vals.sum(dtype=np.int64))
             if (vals == vals[0]).all():
                 S[z0:z1, y0:y1, x0:x1] = vals[0]
                 f += 1
             elif max(x1 - x0, y1 - y0, z1 - z0) <= B:
                 S[z0:z1, y0:y1, x0:x1] = blk
+                stats["iters_leaf"] += int(blk[~surf].sum(dtype=np.int64))
                 lf += 1
             else:
                 s += 1
@@ -350,7 +355,12 @@ def test_uniform_volume_fills_at_level_zero(ref3):
     v = Volume(3.0, 4.0, 3.0, 4.0, 3.0, 4.0, 30, 20, 10, 100, c=(-0.2, 0.6))
     S, st = ref3.subdiv(v, 4, 2, 2)
     assert (S == 1).all()
-    assert st == {"levels": 1, "regions": [64], "fills": [64], "splits": [0], "leaves": [0]}
+    # Every box's whole surface is scanned, at one iteration a voxel. The
+    # boxes are 7, 8, 7, 8 wide, 5 high and 2, 3, 2, 3 deep: only the 3-deep
+    # ones have an inside, (w - 2) * 3 * 1 voxels each.
+    inside = 2 * 4 * (5 + 6 + 5 + 6) * 3
+    assert st == {"levels": 1, "regions": [64], "fills": [64], "splits": [0], "leaves": [0],
+                  "iters_surface": 30 * 20 * 10 - inside, "iters_leaf": 0}
 
 
 def test_bad_arguments(ref3):
