@@ -241,10 +241,14 @@ ask_status ask_dwell_subdiv_noalloc(const ask_window *win, const ask_params *par
  * same form. d_outs[i]: device memory, wins[i].W * wins[i].H uint32,
  * caller-owned; images must not overlap. stats (optional) sums the counters
  * over the batch and makes the call wait, as for ask_dwell_subdiv. The image
- * table is staged through context-owned pinned memory; the call returns
- * once the staging buffer is free for its copy. A batch of more than one
- * image cannot be captured into a graph (ASK_EINVAL on a capturing stream):
- * its table is staged through memory that later calls reuse. */
+ * table and the level-0 seed offsets go to device memory through kernels
+ * that carry them as arguments, so a stream capture records the data: on a
+ * capturing stream the batch gets a table of its own, which no later call
+ * writes and the context frees only when it is destroyed, and the graph
+ * can be replayed as often as wanted; otherwise the batch uses the
+ * context's table, which the next batch on the context overwrites (calls
+ * on different streams must be ordered by the caller). Errors as for
+ * ask_dwell_subdiv, and ASK_ENOMEM when the table cannot be allocated. */
 ask_status ask_dwell_batch(ask_ctx *ctx, uint32_t n, const ask_window *wins,
                            const ask_params *params, uint32_t nparams,
                            uint32_t *const *d_outs, void *stream, ask_stats *stats);
