@@ -306,7 +306,9 @@ def volume_leg(torch, ask, workloads, sp, steps):
         return ms[len(ms) // 2]
 
     log("volume: %s, exhaustive" % (v,))
-    ex_fn = lambda: ask.ask3_dwell_exhaustive(vol, out.data_ptr(), sp)  # noqa: E731
+    ex_work = torch.empty(ask.EXHAUSTIVE3_WORK_BYTES, dtype=torch.uint8, device="cuda")
+    ex_fn = lambda: ask.ask3_dwell_exhaustive(vol, out.data_ptr(), ex_work.data_ptr(),  # noqa: E731
+                                              stream=sp)
     ex_fn()
     ex_ms = timed(ex_fn, 3)
     ex_iters = int(out.to(torch.int64).sum().item())

@@ -73,14 +73,23 @@ typedef struct ask3_stats {
 ask_status ask3_validate(const ask_volume *v, const ask3_params *p);
 
 /* Bytes of device workspace ask3_dwell_subdiv needs for this volume and
- * these parameters: a control block and two level tables of
+ * these parameters: a 36 KiB control block and two level tables of
  * min(W H L, max(level-0 cells, r^3 floor(W H L / (B + 1)))) 8-byte entries
  * each (a split box has a side > B, so at least B + 1 voxels). */
 ask_status ask3_workspace_bytes(const ask_volume *v, const ask3_params *p, uint64_t *bytes);
 
+/* Device workspace of ask3_dwell_exhaustive: the counters through which its
+ * waves claim columns of voxels. */
+#define ASK3_EXHAUSTIVE_WORK_BYTES 1024u
+
 /* Exhaustive volume: every voxel's dwell into d_out (device memory,
- * W * H * L uint32, caller-owned). */
-ask_status ask3_dwell_exhaustive(const ask_volume *v, uint32_t *d_out, void *stream);
+ * W * H * L uint32, caller-owned). d_work: device memory of at least
+ * ASK3_EXHAUSTIVE_WORK_BYTES bytes, 256-byte aligned, caller-owned, not used
+ * by another call until this one has finished on `stream` (the call clears
+ * it first). No allocation and no host synchronisation. Errors: ASK_EINVAL
+ * (volume, buffers), ASK_EDEVICE (no current device, or a launch failed). */
+ask_status ask3_dwell_exhaustive(const ask_volume *v, uint32_t *d_out, void *d_work,
+                                 uint64_t work_bytes, void *stream);
 
 /* Subdivision volume into d_out (as above). d_work: device memory of at
  * least ask3_workspace_bytes bytes, 256-byte aligned, caller-owned, not

@@ -64,6 +64,7 @@ class ask_stats(C.Structure):
 CURVE_CANONICAL, CURVE_MORTON = 0, 1
 CURVES = {"canonical": CURVE_CANONICAL, "morton": CURVE_MORTON}
 MAX_LEVELS3 = 32
+EXHAUSTIVE3_WORK_BYTES = 1024  # ASK3_EXHAUSTIVE_WORK_BYTES
 
 
 class ask_volume(C.Structure):
@@ -124,7 +125,7 @@ SIGNATURES = {
     "ask3_validate": (C.c_int, [C.POINTER(ask_volume), C.POINTER(ask3_params)]),
     "ask3_workspace_bytes": (C.c_int, [C.POINTER(ask_volume), C.POINTER(ask3_params),
                                        C.POINTER(C.c_uint64)]),
-    "ask3_dwell_exhaustive": (C.c_int, [C.POINTER(ask_volume), _P, _P]),
+    "ask3_dwell_exhaustive": (C.c_int, [C.POINTER(ask_volume), _P, _P, C.c_uint64, _P]),
     "ask3_dwell_subdiv": (C.c_int, [C.POINTER(ask_volume), C.POINTER(ask3_params), _P, _P,
                                     C.c_uint64, _P, C.POINTER(ask3_stats)]),
 }
@@ -356,8 +357,10 @@ def ask3_workspace_bytes(vol, prm):
     return n.value
 
 
-def ask3_dwell_exhaustive(vol, d_out, stream=0):
-    _check(lib.ask3_dwell_exhaustive(C.byref(vol), _P(d_out), _P(stream)))
+def ask3_dwell_exhaustive(vol, d_out, d_work, work_bytes=None, stream=0):
+    """d_work: device memory of at least EXHAUSTIVE3_WORK_BYTES bytes."""
+    nbytes = EXHAUSTIVE3_WORK_BYTES if work_bytes is None else work_bytes
+    _check(lib.ask3_dwell_exhaustive(C.byref(vol), _P(d_out), _P(d_work), nbytes, _P(stream)))
 
 
 def ask3_dwell_subdiv(vol, prm, d_out, d_work, work_bytes, stream=0, want_stats=False):

@@ -25,16 +25,21 @@ constexpr uint32_t kWavesPer = kThreads / kLanes;
 
 // Control block, in 64-bit words: entries per level table (one more word
 // than levels: the last level's children slot), then per-level fills,
-// splits and leaves, the overflow flag, and per-level tickets (the next
-// table entry a wave takes).
+// splits and leaves and the overflow flag (the words read back for stats),
+// then per level eight claim counters, one per XCD, each on a 128-byte line
+// of its own.
 constexpr uint32_t kCountW = 0;
 constexpr uint32_t kFillW = 40;
 constexpr uint32_t kSplitW = kFillW + ASK3_MAX_LEVELS;
 constexpr uint32_t kLeafW = kSplitW + ASK3_MAX_LEVELS;
 constexpr uint32_t kOverW = kLeafW + ASK3_MAX_LEVELS;
-constexpr uint32_t kTicketW = kOverW + 8;
-constexpr uint32_t kCtrlWords = kTicketW + ASK3_MAX_LEVELS;
-constexpr uint64_t kTableOffset = 4096;
+constexpr uint32_t kStatWords = kOverW + 8;
+constexpr uint32_t kXcds = 8;         // claim counters per level: one per XCD of MI355X
+constexpr uint32_t kLineWords = 16;   // 128 bytes
+constexpr uint32_t kClaimW = 256;
+constexpr uint32_t kCtrlWords = kClaimW + ASK3_MAX_LEVELS * kXcds * kLineWords;
+constexpr uint64_t kTableOffset = kCtrlWords * 8 + 2048;  // 36864: 256-byte aligned
+static_assert(kStatWords <= kClaimW && kTableOffset % 256 == 0, "control block layout");
 constexpr uint32_t kMaxCoordBits = 21;  // per axis, so that a Morton scalar fits 63 bits
 
 struct Vol3 {
@@ -69,7 +74,8 @@ __device__ __forceinline__ void put_voxel(const Vol3 &v, uint32_t x, uint32_t y,
 // gives each lane one voxel waits for its slowest voxel with most lanes
 // idle. Here every lane iterates its own voxel, and after every stretch of
 // kStride3 iterations the lanes whose voxel has finished take the next
-// voxels of the stream.
+// voxels of the stream. A lane takes a voxel with its first step done and
+// tested, and takes another at once when that voxel escaped there.
 //
 // The dwell: q <- q^2 + c with q = a + b i + e j, c = cr + ci i, the first k
 // with |q_k|^2 > 4, else D; per step a' = (a^2 - (b^2 + e^2)) + cr,
@@ -96,9 +102,10 @@ __device__ __forceinline__ void put_voxel(const Vol3 &v, uint32_t x, uint32_t y,
 // surface telling whether it was one of the first n_surf stream positions.
 // A surface stream (kSurface) takes positions [0, n_surf) first and decides
 // whether their dwells are all equal as it goes: once some voxel has
-// finished with dwell v (the least of the first stretch in which any
-// finished), another finishing with a different dwell, or one still running
-// after v iterations, shows the surface is mixed. It then stops (n_all ==
+// finished with dwell v (1 if one escaped at its first step, else the least
+// of the first stretch in which any finished), another finishing with a
+// different dwell, or one still running after v iterations, shows the
+// surface is mixed. It then stops (n_all ==
 // n_surf), or (n_all > n_surf: a leaf box) goes on with the surface's other
 // positions and then positions [n_surf, n_all), the box's inside. Returns
 // 0 for a uniform surface (dwell v), 1 for a mixed one that stopped, 2 for a
@@ -131,6 +138,7 @@ __device__ __forceinline__ uint32_t quat_stream(const Vol3 &v, uint32_t n_surf, 
     double a = 0.0, b = 0.0, e = 0.0, a2 = 0.0, s2 = 0.0;
     for (;;) {
         unsigned long long idle = __ballot(!have);
+        bool ones = false;  // this lane finished a voxel at its first step
         while (idle && next < n) {
             if (!have) {
                 const uint32_t j = next + (uint32_t)__builtin_amdgcn_mbcnt_hi(
@@ -144,11 +152,37 @@ __device__ __forceinline__ uint32_t quat_stream(const Vol3 &v, uint32_t n_surf, 
                     e = axis_point(v.cz, v.hz, z, v.n[2]);
                     a2 = a * a;
                     s2 = b * b + e * e;
-                    k = 0;
+                    // The first step, tested here: most voxels of a volume
+                    // lie outside the set and escape at once, and such a
+                    // lane takes its next voxel in the same refill instead
+                    // of holding a whole stretch.
+                    quat_step(a, b, e, a2, s2, cr, ci);
+                    k = 1;
+                    if (a2 + s2 > 4.0) {
+                        done(x, y, z, 1u, surf);
+                        have = false;
+                        ones = true;
+                    }
                 }
             }
             next = min(n, next + (uint32_t)__popcll(idle));
             idle = __ballot(!have);
+        }
+        // A surface voxel that escaped at the first step has dwell 1, the
+        // least there is: it sets v when none is set yet, and then any
+        // voxel still running (k >= 1) or a v above 1 shows a mixed surface.
+        if (kSurface && scanning && __ballot(ones)) {
+            if (!vset) {
+                val = 1;
+                vset = true;
+            }
+            if (val != 1 || __ballot(have)) {
+                if (n_all == n_surf)
+                    return 1;
+                scanning = false;
+                n = n_all;
+                continue;
+            }
         }
         if (__ballot(have) == 0)
             break;
@@ -306,6 +340,22 @@ __device__ __forceinline__ uint64_t wave_base(unsigned long long *counter, uint6
     return uniform64_3(base);
 }
 
+// The XCD this wave runs on (HW_REG_XCC_ID). Only the claim order depends
+// on it: every counter is drained by somebody whatever it reads.
+__device__ __forceinline__ uint32_t xcd_id() {
+    return __builtin_amdgcn_s_getreg((3 << 11) | 20) & (kXcds - 1);
+}
+
+// Items [0, n) claimed by the waves of a persistent grid: item i belongs to
+// counter i mod kXcds (at counters[x * stride]), a wave drains its own
+// XCD's counter `chunk` items per atomic add, then the others' in turn, and
+// calls item(i) for every item it claimed. One counter address serves one
+// atomic at a time (about 11 ns apart on MI355X), eight serve six times as
+// many, and no wave starts past the last item.
+template <class Item>
+__device__ __forceinline__ void claim_items(unsigned long long *counters, uint32_t stride,
+                                            uint64_t n, uint64_t chunk, Item item);
+
 // One atomic add of n; every lane gets the counter's old value.
 __device__ __forceinline__ uint64_t wave_claim(unsigned long long *counter, uint64_t n,
                                                uint32_t) {
@@ -313,6 +363,24 @@ __device__ __forceinline__ uint64_t wave_claim(unsigned long long *counter, uint
     if (first_lane3())
         base = atomicAdd(counter, (unsigned long long)n);
     return uniform64_3(base);
+}
+
+template <class Item>
+__device__ __forceinline__ void claim_items(unsigned long long *counters, uint32_t stride,
+                                            uint64_t n, uint64_t chunk, Item item) {
+    const uint32_t home = xcd_id();
+    for (uint32_t q = 0; q < kXcds; ++q) {
+        const uint32_t x = (home + q) & (kXcds - 1);
+        const uint64_t mine = n > x ? (n - x + kXcds - 1) / kXcds : 0;  // items x, x + 8, ...
+        for (;;) {
+            const uint64_t k0 = wave_claim(&counters[x * stride], chunk, 0);
+            if (k0 >= mine)
+                break;
+            const uint64_t k1 = std::min(k0 + chunk, mine);
+            for (uint64_t k = k0; k < k1; ++k)
+                item(x + k * kXcds);
+        }
+    }
 }
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask, uint32_t lane) {
@@ -323,31 +391,43 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask, uint32_t lane) {
 // Kernels
 // ---------------------------------------------------------------------------
 
-// Every voxel: each wave streams the voxels of one kTile3 x kTile3 tile of a
-// z slice (row by row, lane refilled), kEx3Waves waves per workgroup.
-constexpr uint32_t kTile3 = 32;
+// Every voxel: the volume is cut into columns of kTile3 x kTile3 x kCol3
+// voxels, and the waves of a grid that the device holds at once claim them
+// (per-XCD counters in the caller's workspace) and stream each column's
+// voxels, slice by slice and row by row, lane refilled. Most voxels of a
+// volume escape within a step or two, so a wave per column lives only a few
+// microseconds, and the hardware then starts new waves far more slowly than
+// they end (a wave trace showed 1 300 to 2 800 of the 8 192 wave slots in
+// use); waves that stay and claim work keep every slot busy.
+constexpr uint32_t kTile3 = 16;
+constexpr uint32_t kCol3 = 2;
 constexpr uint32_t kEx3Waves = 4;
 
 __global__ __launch_bounds__(kEx3Waves * kLanes) void exhaustive3_kernel(Vol3 v, uint32_t tiles_x,
-                                                               uint32_t tiles_y, uint64_t tiles) {
-    const uint64_t t = (uint64_t)blockIdx.x * kEx3Waves + threadIdx.x / kLanes;
-    if (t >= tiles)
-        return;
-    const uint32_t bx = (uint32_t)(t % tiles_x);
-    const uint32_t by = (uint32_t)((t / tiles_x) % tiles_y);
-    const uint32_t z = (uint32_t)(t / ((uint64_t)tiles_x * tiles_y));
-    const uint32_t x0 = bx * kTile3, y0 = by * kTile3;
-    uint32_t val = 0;
-    quat_stream<false>(
-        v, 0u, kTile3 * kTile3,
-        [&](uint32_t i, uint32_t &x, uint32_t &y, uint32_t &zz) {
-            x = x0 + i % kTile3;
-            y = y0 + i / kTile3;
-            zz = z;
-            return x < v.n[0] && y < v.n[1];
-        },
-        [&](uint32_t x, uint32_t y, uint32_t zz, uint32_t d, bool) { put_voxel(v, x, y, zz, d); },
-        val);
+                                                                uint32_t tiles_y, uint32_t cols,
+                                                                unsigned long long *counters) {
+    claim_items(counters, kLineWords, cols, 1, [&](uint64_t c) {
+        const uint32_t t = (uint32_t)c;
+        const uint32_t rest = t / tiles_x;
+        const uint32_t x0 = (t % tiles_x) * kTile3, y0 = (rest % tiles_y) * kTile3;
+        const uint32_t z0 = (rest / tiles_y) * kCol3;
+        uint32_t val = 0;
+        quat_stream<false>(
+            v, 0u, kTile3 * kTile3 * kCol3,
+            [&](uint32_t i, uint32_t &x, uint32_t &y, uint32_t &zz) {
+                x = x0 + i % kTile3;
+                y = y0 + (i / kTile3) % kTile3;
+                zz = z0 + i / (kTile3 * kTile3);
+                return x < v.n[0] && y < v.n[1] && zz < v.n[2];
+            },
+            [&](uint32_t x, uint32_t y, uint32_t zz, uint32_t d, bool) { put_voxel(v, x, y, zz, d); },
+            val);
+    });
+}
+
+__global__ __launch_bounds__(kThreads) void clear3_kernel(unsigned long long *w, uint32_t n) {
+    for (uint32_t i = threadIdx.x; i < n; i += kThreads)
+        w[i] = 0;
 }
 
 __global__ __launch_bounds__(kThreads) void reset3_kernel(unsigned long long *ctrl) {
@@ -431,97 +511,92 @@ __global__ __launch_bounds__(kThreads) void level3_kernel(Vol3 v, Level3 L) {
     const uint32_t lane = threadIdx.x & (kLanes - 1);
     const uint64_t count = std::min((uint64_t)L.ctrl[kCountW + L.level], L.cap);
     // Entries per claim: one while the level has few boxes per wave (the best
-    // balance), up to 64 when it has very many small ones, so that the one
-    // counter address does not serialise the level.
+    // balance), up to 64 when it has very many small ones, so that the
+    // counters do not serialise the level.
     const uint64_t waves = (uint64_t)gridDim.x * kWavesPer;
     const uint64_t chunk = std::max<uint64_t>(1, std::min<uint64_t>(64, count / (waves * 16)));
     unsigned long long nfill = 0, nsplit = 0, nleaf = 0;
-    for (;;) {
-        const uint64_t e0 = wave_claim(&L.ctrl[kTicketW + L.level], chunk, lane);
-        if (e0 >= count)
-            break;
-        const uint64_t e1 = std::min(e0 + chunk, count);
-        for (uint64_t e = e0; e < e1; ++e) {
-            uint32_t p[3], lo[3], hi[3];
-            scalar_cell(uniform64_3(L.in[e]), L.G, L.curve, p);  // wave-uniform box
-            if (!cell_box(v, L.G, p, lo, hi)) {
-                if (lane == 0)
-                    atomicOr(&L.ctrl[kOverW], 2ull);
-                continue;
-            }
-            const uint32_t w = hi[0] - lo[0], h = hi[1] - lo[1], l = hi[2] - lo[2];
-            const uint32_t S = surface_count(w, h, l);
-            const bool leaf_size = w <= L.B && h <= L.B && l <= L.B;
-            // The surface in a spread order (64 arcs, offsets within an arc
-            // in bit-reversed round order, as for 2-D rings), so a mixed
-            // surface shows it early; a leaf box's stream goes on into its
-            // inside. Every finished surface dwell is written: whatever
-            // follows, a voxel on a scanned surface ends with its own dwell.
-            const uint32_t q = (S + kLanes - 1) / kLanes;
-            const uint32_t bits = q > 1 ? 32u - (uint32_t)__builtin_clz(q - 1) : 0u;
-            const uint32_t n_surf = kLanes << bits;
-            const uint32_t iw = w > 2 ? w - 2 : 0, ih = h > 2 ? h - 2 : 0, il = l > 2 ? l - 2 : 0;
-            const uint32_t iwh = iw * ih, inside = (w <= 2 || h <= 2 || l <= 2) ? 0u : iwh * il;
-            uint32_t first = 0;
-            const uint32_t outcome = quat_stream<true>(
-                v, n_surf, leaf_size ? n_surf + inside + 1u : n_surf,
-                [&](uint32_t j, uint32_t &x, uint32_t &y, uint32_t &z) {
-                    if (j >= n_surf) {
-                        const uint32_t t = j - n_surf;
-                        if (t >= inside)
-                            return false;
-                        x = lo[0] + 1 + t % iw;
-                        y = lo[1] + 1 + (t / iw) % ih;
-                        z = lo[2] + 1 + t / iwh;
-                        return true;
-                    }
-                    const uint32_t round = j / kLanes;
-                    const uint32_t off = bits ? __brev(round) >> (32u - bits) : 0u;
-                    const uint32_t t = (j % kLanes) * q + off;
-                    if (off >= q || t >= S)
-                        return false;
-                    surface_voxel(t, w, h, l, x, y, z);
-                    x += lo[0];
-                    y += lo[1];
-                    z += lo[2];
-                    return true;
-                },
-                [&](uint32_t x, uint32_t y, uint32_t z, uint32_t d, bool) { put_voxel(v, x, y, z, d); },
-                first);
-            const uint32_t wh = w * h, n = wh * l;
-            if (outcome == 0) {
-                for (uint32_t t = lane; t < n; t += kLanes)
-                    put_voxel(v, lo[0] + t % w, lo[1] + (t / w) % h, lo[2] + t / wh, first);
-                ++nfill;
-            } else if (leaf_size) {
-                ++nleaf;
-            } else {
-                const uint32_t r = L.r, kids = r * r * r;
-                const uint64_t G1 = L.G * r;
-                for (uint32_t k0 = 0; k0 < kids; k0 += kLanes) {
-                    const uint32_t k = k0 + lane;
-                    uint32_t c[3] = {0, 0, 0}, clo[3], chi[3];
-                    bool ok = false;
-                    if (k < kids) {
-                        c[0] = p[0] * r + k % r;
-                        c[1] = p[1] * r + (k / r) % r;
-                        c[2] = p[2] * r + k / (r * r);
-                        ok = cell_box(v, G1, c, clo, chi);
-                    }
-                    const uint64_t mask = __ballot(ok);
-                    const uint64_t base = wave_base(&L.ctrl[kCountW + L.level + 1], mask, lane);
-                    if (ok) {
-                        const uint64_t at = base + lanes_below(mask, lane);
-                        if (at < L.cap)
-                            L.next[at] = cell_scalar(c, G1, L.curve);
-                        else
-                            atomicOr(&L.ctrl[kOverW], 1ull);
-                    }
-                }
-                ++nsplit;
-            }
+    claim_items(&L.ctrl[kClaimW + L.level * kXcds * kLineWords], kLineWords, count, chunk,
+                [&](uint64_t e) {
+        uint32_t p[3], lo[3], hi[3];
+        scalar_cell(uniform64_3(L.in[e]), L.G, L.curve, p);  // wave-uniform box
+        if (!cell_box(v, L.G, p, lo, hi)) {
+            if (lane == 0)
+                atomicOr(&L.ctrl[kOverW], 2ull);
+            return;
         }
-    }
+        const uint32_t w = hi[0] - lo[0], h = hi[1] - lo[1], l = hi[2] - lo[2];
+        const uint32_t S = surface_count(w, h, l);
+        const bool leaf_size = w <= L.B && h <= L.B && l <= L.B;
+        // The surface in a spread order (64 arcs, offsets within an arc
+        // in bit-reversed round order, as for 2-D rings), so a mixed
+        // surface shows it early; a leaf box's stream goes on into its
+        // inside. Every finished surface dwell is written: whatever
+        // follows, a voxel on a scanned surface ends with its own dwell.
+        const uint32_t q = (S + kLanes - 1) / kLanes;
+        const uint32_t bits = q > 1 ? 32u - (uint32_t)__builtin_clz(q - 1) : 0u;
+        const uint32_t n_surf = kLanes << bits;
+        const uint32_t iw = w > 2 ? w - 2 : 0, ih = h > 2 ? h - 2 : 0, il = l > 2 ? l - 2 : 0;
+        const uint32_t iwh = iw * ih, inside = (w <= 2 || h <= 2 || l <= 2) ? 0u : iwh * il;
+        uint32_t first = 0;
+        const uint32_t outcome = quat_stream<true>(
+            v, n_surf, leaf_size ? n_surf + inside + 1u : n_surf,
+            [&](uint32_t j, uint32_t &x, uint32_t &y, uint32_t &z) {
+                if (j >= n_surf) {
+                    const uint32_t t = j - n_surf;
+                    if (t >= inside)
+                        return false;
+                    x = lo[0] + 1 + t % iw;
+                    y = lo[1] + 1 + (t / iw) % ih;
+                    z = lo[2] + 1 + t / iwh;
+                    return true;
+                }
+                const uint32_t round = j / kLanes;
+                const uint32_t off = bits ? __brev(round) >> (32u - bits) : 0u;
+                const uint32_t t = (j % kLanes) * q + off;
+                if (off >= q || t >= S)
+                    return false;
+                surface_voxel(t, w, h, l, x, y, z);
+                x += lo[0];
+                y += lo[1];
+                z += lo[2];
+                return true;
+            },
+            [&](uint32_t x, uint32_t y, uint32_t z, uint32_t d, bool) { put_voxel(v, x, y, z, d); },
+            first);
+        const uint32_t wh = w * h, n = wh * l;
+        if (outcome == 0) {
+            for (uint32_t t = lane; t < n; t += kLanes)
+                put_voxel(v, lo[0] + t % w, lo[1] + (t / w) % h, lo[2] + t / wh, first);
+            ++nfill;
+        } else if (leaf_size) {
+            ++nleaf;
+        } else {
+            const uint32_t r = L.r, kids = r * r * r;
+            const uint64_t G1 = L.G * r;
+            for (uint32_t k0 = 0; k0 < kids; k0 += kLanes) {
+                const uint32_t k = k0 + lane;
+                uint32_t c[3] = {0, 0, 0}, clo[3], chi[3];
+                bool ok = false;
+                if (k < kids) {
+                    c[0] = p[0] * r + k % r;
+                    c[1] = p[1] * r + (k / r) % r;
+                    c[2] = p[2] * r + k / (r * r);
+                    ok = cell_box(v, G1, c, clo, chi);
+                }
+                const uint64_t mask = __ballot(ok);
+                const uint64_t base = wave_base(&L.ctrl[kCountW + L.level + 1], mask, lane);
+                if (ok) {
+                    const uint64_t at = base + lanes_below(mask, lane);
+                    if (at < L.cap)
+                        L.next[at] = cell_scalar(c, G1, L.curve);
+                    else
+                        atomicOr(&L.ctrl[kOverW], 1ull);
+                }
+            }
+            ++nsplit;
+        }
+    });
     if (lane == 0) {
         if (nfill)
             atomicAdd(&L.ctrl[kFillW + L.level], nfill);
@@ -622,16 +697,32 @@ extern "C" ask_status ask3_workspace_bytes(const ask_volume *v, const ask3_param
     return ASK_OK;
 }
 
-extern "C" ask_status ask3_dwell_exhaustive(const ask_volume *v, uint32_t *d_out, void *stream) {
-    if (!volume_ok(v) || !d_out)
+extern "C" ask_status ask3_dwell_exhaustive(const ask_volume *v, uint32_t *d_out, void *d_work,
+                                           uint64_t work_bytes, void *stream) {
+    if (!volume_ok(v) || !d_out || !d_work || ((uintptr_t)d_work & 255) ||
+        work_bytes < ASK3_EXHAUSTIVE_WORK_BYTES)
         return ASK_EINVAL;
+    static_assert(kXcds * kLineWords * 8 <= ASK3_EXHAUSTIVE_WORK_BYTES, "exhaustive workspace");
+    // at most 2^31 voxels, so fewer than 2^31 columns
     const uint32_t tx = (v->W + kTile3 - 1) / kTile3, ty = (v->H + kTile3 - 1) / kTile3;
-    const uint64_t tiles = (uint64_t)tx * ty * v->L;
-    const uint64_t blocks = (tiles + kEx3Waves - 1) / kEx3Waves;
-    if (blocks >= (1ull << 31))
-        return ASK_EINVAL;
-    hipLaunchKernelGGL(exhaustive3_kernel, dim3((uint32_t)blocks), dim3(kEx3Waves * kLanes), 0,
-                       (hipStream_t)stream, make_vol(v, d_out), tx, ty, tiles);
+    const uint64_t cols = (uint64_t)tx * ty * ((v->L + kCol3 - 1) / kCol3);
+    int dev = 0, cus = 0, occ = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+        return ASK_EDEVICE;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, exhaustive3_kernel, kEx3Waves * kLanes,
+                                                     0) != hipSuccess ||
+        occ < 1) {
+        (void)hipGetLastError();
+        occ = 1;
+    }
+    const uint64_t blocks = std::min<uint64_t>((cols + kEx3Waves - 1) / kEx3Waves, (uint64_t)cus * occ);
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long *counters = (unsigned long long *)d_work;
+    hipLaunchKernelGGL(clear3_kernel, dim3(1), dim3(kThreads), 0, s, counters, kXcds * kLineWords);
+    hipLaunchKernelGGL(exhaustive3_kernel, dim3((uint32_t)blocks), dim3(kEx3Waves * kLanes), 0, s,
+                       make_vol(v, d_out), tx, ty, (uint32_t)cols, counters);
     return launched();
 }
 
@@ -690,7 +781,7 @@ extern "C" ask_status ask3_dwell_subdiv(const ask_volume *v, const ask3_params *
     ask_status st = launched();
     if (st != ASK_OK || !stats)
         return st;
-    unsigned long long host[kCtrlWords];
+    unsigned long long host[kStatWords];
     if (hipMemcpyAsync(host, ctrl, sizeof host, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return ASK_EDEVICE;

@@ -49,8 +49,9 @@ def ref3():
 def gpu_exhaustive(lib3, v):
     ask, torch = lib3
     out = torch.zeros(v.voxels, dtype=torch.int32, device="cuda")
-    ask.ask3_dwell_exhaustive(ask.volume(v), out.data_ptr(),
-                              torch.cuda.current_stream().cuda_stream)
+    work = torch.empty(ask.EXHAUSTIVE3_WORK_BYTES, dtype=torch.uint8, device="cuda")
+    ask.ask3_dwell_exhaustive(ask.volume(v), out.data_ptr(), work.data_ptr(),
+                              stream=torch.cuda.current_stream().cuda_stream)
     torch.cuda.synchronize()
     return out
 
