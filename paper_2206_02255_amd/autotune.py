@@ -411,6 +411,56 @@ def tune_class(ctx, name, log=print):
     return key, entry
 
 
+VOLUME_GRID = [(32, 2, 8), (32, 2, 16), (16, 2, 16), (64, 2, 8), (16, 4, 8), (64, 2, 4),
+               (16, 2, 8), (32, 4, 4), (8, 2, 16), (64, 2, 16)]
+
+
+def volume_sweep(v, grid=VOLUME_GRID, curve="morton", reps=7, log=print):
+    """Kernel time (median of reps renders, HIP events on the stream) of the
+    3-D subdivision volume for each (g, r, B) of grid, and of the exhaustive
+    volume, with the voxels where each subdivision volume differs from the
+    exhaustive one."""
+    import torch
+    vol = ask.volume(v)
+    sp = torch.cuda.current_stream().cuda_stream
+    out = torch.empty(v.voxels, dtype=torch.int32, device="cuda")
+    ex = torch.empty(v.voxels, dtype=torch.int32, device="cuda")
+    wk = torch.empty(ask.EXHAUSTIVE3_WORK_BYTES, dtype=torch.uint8, device="cuda")
+
+    def timed(fn):
+        ms = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            b.synchronize()
+            ms.append(a.elapsed_time(b))
+        return sorted(ms)[len(ms) // 2]
+
+    def exf():
+        ask.ask3_dwell_exhaustive(vol, ex.data_ptr(), wk.data_ptr(), stream=sp)
+    exf()
+    res = {"exhaustive_ms": timed(exf), "rows": []}
+    log("exhaustive %.3f ms" % res["exhaustive_ms"])
+    for g, r, B in grid:
+        prm = ask.params3(g, r, B, curve)
+        nb = ask.ask3_workspace_bytes(vol, prm)
+        work = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        st = ask.ask3_dwell_subdiv(vol, prm, out.data_ptr(), work.data_ptr(), nb, sp,
+                                   want_stats=True)
+
+        def fn():
+            ask.ask3_dwell_subdiv(vol, prm, out.data_ptr(), work.data_ptr(), nb, sp)
+        row = {"g": g, "r": r, "B": B, "ms": timed(fn), "regions": st["regions"],
+               "differ": int((out != ex).sum().item())}
+        res["rows"].append(row)
+        log("(%d, %d, %d) %.3f ms, regions %s, voxels differing %d"
+            % (g, r, B, row["ms"], row["regions"], row["differ"]))
+        del work
+    return res
+
+
 def main(argv=None):
     import torch
     ap = argparse.ArgumentParser(description="(g, r, B) sweep on the paper's window")
@@ -428,12 +478,20 @@ def main(argv=None):
     ap.add_argument("--prior", default=None, nargs="+", metavar="PILOT,TOP",
                     help="also run the model-guided search (PILOT pilot renders, then the TOP "
                          "best predicted) against the full sweep's measurements, for each pair")
+    ap.add_argument("--volume", action="store_true",
+                    help="sweep (g, r, B) of the 3-D subdivision of the benchmark's volume")
     ap.add_argument("--window", default="paper", choices=["paper", "deep", "julia"],
                     help="--schemes: the paper's window (--size, --dwell), the deep zoom "
                          "or the Julia-set workload")
     args = ap.parse_args(argv)
     import workloads
     from workloads import LARGE_SWEEP, paper_window
+    if args.volume:
+        res = volume_sweep(workloads.VOLUME, log=lambda m: print(m, flush=True))
+        if args.json:
+            with open(args.json, "w") as f:
+                json.dump(res, f, indent=1)
+        return
     if args.tune:
         ctx = ask.ask_create(0)
         try:

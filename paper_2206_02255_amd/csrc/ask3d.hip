@@ -465,6 +465,23 @@ __global__ __launch_bounds__(kThreads) void seed3_kernel(Vol3 v, uint64_t *table
     }
 }
 
+// Division by a divisor fixed for a whole box (a side, a face, a ring):
+// its binary64 reciprocal is taken once, and n * r, within a relative
+// 2^-52 of n / d, truncates to the quotient or one off it, which the
+// remainder corrects. Exact for n < 2^31 and 1 <= d < 2^31, in a few
+// instructions instead of an integer division sequence per voxel.
+struct Div {
+    uint32_t d;
+    double r;
+    __device__ explicit Div(uint32_t d_) : d(d_), r(1.0 / (double)d_) {}
+    __device__ __forceinline__ uint32_t div(uint32_t n) const {
+        uint32_t q = (uint32_t)((double)n * r);
+        const int32_t rem = (int32_t)(n - q * d);
+        q = rem < 0 ? q - 1 : (rem >= (int32_t)d ? q + 1 : q);
+        return q;
+    }
+};
+
 // Voxel t of the surface of a w x h x l box: the two z faces, then the
 // rectangular ring of each inner slice. A box with a side of 1 or 2 is all
 // surface and is walked in storage order.
@@ -474,34 +491,73 @@ __device__ __forceinline__ uint32_t surface_count(uint32_t w, uint32_t h, uint32
     return 2 * w * h + (l - 2) * (2 * w + 2 * (h - 2));
 }
 
-__device__ __forceinline__ void surface_voxel(uint32_t t, uint32_t w, uint32_t h, uint32_t l,
-                                              uint32_t &x, uint32_t &y, uint32_t &z) {
-    if (w <= 2 || h <= 2 || l <= 2) {
-        x = t % w;
-        y = (t / w) % h;
-        z = t / (w * h);
+struct Surface {
+    uint32_t w, h, l, face;
+    bool thin;
+    Div dw, dh, dring;
+    __device__ Surface(uint32_t w_, uint32_t h_, uint32_t l_)
+        : w(w_), h(h_), l(l_), face(w_ * h_), thin(w_ <= 2 || h_ <= 2 || l_ <= 2), dw(w_),
+          dh(h_), dring(thin ? 1u : 2 * w_ + 2 * (h_ - 2)) {}
+
+    __device__ __forceinline__ void voxel(uint32_t t, uint32_t &x, uint32_t &y, uint32_t &z) const {
+        if (thin) {
+            const uint32_t row = dw.div(t);
+            x = t - row * w;
+            z = dh.div(row);
+            y = row - z * h;
+            return;
+        }
+        if (t < 2 * face) {
+            z = t < face ? 0 : l - 1;
+            t = t < face ? t : t - face;
+            y = dw.div(t);
+            x = t - y * w;
+            return;
+        }
+        const uint32_t u = t - 2 * face;
+        const uint32_t zi = dring.div(u);
+        z = 1 + zi;
+        const uint32_t q = u - zi * dring.d;
+        if (q < w) {
+            x = q, y = 0;
+        } else if (q < 2 * w) {
+            x = q - w, y = h - 1;
+        } else {
+            const uint32_t q2 = q - 2 * w;
+            x = (q2 & 1) ? w - 1 : 0;
+            y = 1 + q2 / 2;
+        }
+    }
+};
+
+// T: every voxel of the box (lo, w x h x l) takes dwell d. With w <= 64 the
+// lanes hold a column x each and walk rows (y fastest, then z) 64 / w
+// rows apart, so no voxel needs a division.
+__device__ void fill_box(const Vol3 &v, const uint32_t lo[3], uint32_t w, uint32_t h,
+                         uint32_t l, uint32_t d, uint32_t lane) {
+    if (w > kLanes) {
+        for (uint32_t z = 0; z < l; ++z)
+            for (uint32_t y = 0; y < h; ++y)
+                for (uint32_t x = lane; x < w; x += kLanes)
+                    put_voxel(v, lo[0] + x, lo[1] + y, lo[2] + z, d);
         return;
     }
-    const uint32_t face = w * h;
-    if (t < 2 * face) {
-        z = t < face ? 0 : l - 1;
-        t = t < face ? t : t - face;
-        x = t % w;
-        y = t / w;
+    const uint32_t rows = kLanes / w;
+    const uint32_t x = lane % w;
+    uint32_t y = lane / w, z = 0;
+    if (y >= rows)
         return;
+    while (y >= h) {
+        y -= h;
+        ++z;
     }
-    const uint32_t ring = 2 * w + 2 * (h - 2);
-    const uint32_t u = t - 2 * face;
-    z = 1 + u / ring;
-    const uint32_t q = u % ring;
-    if (q < w) {
-        x = q, y = 0;
-    } else if (q < 2 * w) {
-        x = q - w, y = h - 1;
-    } else {
-        const uint32_t q2 = q - 2 * w;
-        x = (q2 & 1) ? w - 1 : 0;
-        y = 1 + q2 / 2;
+    while (z < l) {
+        put_voxel(v, lo[0] + x, lo[1] + y, lo[2] + z, d);
+        y += rows;
+        while (y >= h) {
+            y -= h;
+            ++z;
+        }
     }
 }
 
@@ -528,16 +584,23 @@ __global__ __launch_bounds__(kThreads) void level3_kernel(Vol3 v, Level3 L) {
         const uint32_t w = hi[0] - lo[0], h = hi[1] - lo[1], l = hi[2] - lo[2];
         const uint32_t S = surface_count(w, h, l);
         const bool leaf_size = w <= L.B && h <= L.B && l <= L.B;
-        // The surface in a spread order (64 arcs, offsets within an arc
-        // in bit-reversed round order, as for 2-D rings), so a mixed
-        // surface shows it early; a leaf box's stream goes on into its
-        // inside. Every finished surface dwell is written: whatever
-        // follows, a voxel on a scanned surface ends with its own dwell.
-        const uint32_t q = (S + kLanes - 1) / kLanes;
-        const uint32_t bits = q > 1 ? 32u - (uint32_t)__builtin_clz(q - 1) : 0u;
-        const uint32_t n_surf = kLanes << bits;
-        const uint32_t iw = w > 2 ? w - 2 : 0, ih = h > 2 ? h - 2 : 0, il = l > 2 ? l - 2 : 0;
-        const uint32_t iwh = iw * ih, inside = (w <= 2 || h <= 2 || l <= 2) ? 0u : iwh * il;
+        // The surface in a spread order, so that a mixed surface shows it
+        // early: A arcs of 2^bits voxels (A between 64 and 128 once the
+        // surface has 64 voxels or more), one voxel of every arc per round,
+        // at offsets taken in bit-reversed round order (0, 1/2, 1/4, 3/4,
+        // ... of an arc), so that only the last arc's tail names no voxel.
+        // A leaf box's stream goes on into its inside. Every finished
+        // surface dwell is written: whatever follows, a voxel on a scanned
+        // surface ends with its own dwell.
+        const uint32_t bits = S >= 2 * kLanes ? 31u - (uint32_t)__builtin_clz(S / kLanes) : 0u;
+        const uint32_t arcs = (S + (1u << bits) - 1) >> bits;
+        const Div darcs(arcs);
+        const uint32_t n_surf = arcs << bits;
+        const bool thin = w <= 2 || h <= 2 || l <= 2;
+        const uint32_t iw = thin ? 1u : w - 2, ih = thin ? 1u : h - 2;
+        const uint32_t inside = thin ? 0u : iw * ih * (l - 2);
+        const Surface surf(w, h, l);
+        const Div diw(iw), dih(ih);
         uint32_t first = 0;
         const uint32_t outcome = quat_stream<true>(
             v, n_surf, leaf_size ? n_surf + inside + 1u : n_surf,
@@ -546,17 +609,18 @@ __global__ __launch_bounds__(kThreads) void level3_kernel(Vol3 v, Level3 L) {
                     const uint32_t t = j - n_surf;
                     if (t >= inside)
                         return false;
-                    x = lo[0] + 1 + t % iw;
-                    y = lo[1] + 1 + (t / iw) % ih;
-                    z = lo[2] + 1 + t / iwh;
+                    const uint32_t row = diw.div(t), zi = dih.div(row);
+                    x = lo[0] + 1 + (t - row * iw);
+                    y = lo[1] + 1 + (row - zi * ih);
+                    z = lo[2] + 1 + zi;
                     return true;
                 }
-                const uint32_t round = j / kLanes;
+                const uint32_t round = darcs.div(j);
                 const uint32_t off = bits ? __brev(round) >> (32u - bits) : 0u;
-                const uint32_t t = (j % kLanes) * q + off;
-                if (off >= q || t >= S)
+                const uint32_t t = ((j - round * arcs) << bits) + off;
+                if (t >= S)
                     return false;
-                surface_voxel(t, w, h, l, x, y, z);
+                surf.voxel(t, x, y, z);
                 x += lo[0];
                 y += lo[1];
                 z += lo[2];
@@ -564,10 +628,8 @@ __global__ __launch_bounds__(kThreads) void level3_kernel(Vol3 v, Level3 L) {
             },
             [&](uint32_t x, uint32_t y, uint32_t z, uint32_t d, bool) { put_voxel(v, x, y, z, d); },
             first);
-        const uint32_t wh = w * h, n = wh * l;
         if (outcome == 0) {
-            for (uint32_t t = lane; t < n; t += kLanes)
-                put_voxel(v, lo[0] + t % w, lo[1] + (t / w) % h, lo[2] + t / wh, first);
+            fill_box(v, lo, w, h, l, first, lane);
             ++nfill;
         } else if (leaf_size) {
             ++nleaf;
