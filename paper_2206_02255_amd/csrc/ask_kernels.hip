@@ -756,7 +756,8 @@ __global__ __launch_bounds__(kBlock) void level_exact_kernel(SubdivArgs a, uint3
 //
 // Waiting is cheap on purpose: the slot's tag and `pending` are read with
 // relaxed loads (no cache invalidation), with a growing pause between reads,
-// and a single acquire fence follows once the tag is seen. Every wait is also
+// and once the tag is seen the entry's fields are read with device-scope
+// loads, past the XCD's L2, instead of an acquire fence. Every wait is also
 // bounded in wall-clock time: a wave that waits longer than a.wait_ticks of
 // the constant-rate clock records a timeout and leaves, so the grid always
 // drains.
