@@ -111,7 +111,7 @@ __device__ __forceinline__ void put_voxel(const Vol3 &v, uint32_t x, uint32_t y,
 // 0 for a uniform surface (dwell v), 1 for a mixed one that stopped, 2 for a
 // mixed one whose leaf was completed (and 2 for plain streams).
 // ---------------------------------------------------------------------------
-constexpr uint32_t kStride3 = 8;
+constexpr uint32_t kStride3 = 16;
 
 // One step of the orbit; s2 = b^2 + e^2 of the new q.
 __device__ __forceinline__ void quat_step(double &a, double &b, double &e, double &a2, double &s2,
