@@ -3,12 +3,13 @@
 // subdivision volumes of the quaternion Julia set, the level tables holding
 // one space-filling-curve scalar per box (canonical or Morton order).
 //
-// One wave per box, each wave claiming the next entries of its level's table
-// by ticket (one atomic per box, or per chunk of boxes on levels with very
-// many), so a level launch needs no count from the host and waves that drew
-// cheap boxes take more: the host knows in advance the
-// last level any box can reach (the first whose cells all have sides <= B)
-// and launches that many level kernels back to back, with no read-back.
+// One wave per box: the waves the device holds at once claim the entries
+// of their level's table from eight counters, one per XCD (a box or a chunk
+// of boxes per atomic), so a level launch needs no count from the host and
+// waves that drew cheap boxes take more. The host knows in advance the last
+// level any box can reach (the first whose cells all have sides <= B) and
+// launches that many level kernels back to back, with no read-back. The
+// exhaustive volume is claimed the same way, in columns of voxels.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
