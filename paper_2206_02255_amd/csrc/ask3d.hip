@@ -125,9 +125,18 @@ __device__ __forceinline__ void quat_step(double &a, double &b, double &e, doubl
     s2 = b * b + e * e;
 }
 
-template <bool kSurface, class VoxelOf, class Done>
+// The surface decision of one wave alone: v is the wave's own.
+struct SoloDecision {
+    __device__ uint32_t propose(uint32_t v) const { return v; }
+    __device__ bool known(uint32_t &) const { return false; }
+    __device__ bool mixed() const { return false; }
+    __device__ void set_mixed() const {}
+};
+
+template <bool kSurface, class VoxelOf, class Done, class Decision = SoloDecision>
 __device__ __forceinline__ uint32_t quat_stream(const Vol3 &v, uint32_t n_surf, uint32_t n_all,
-                                                VoxelOf voxel_of, Done done, uint32_t &val) {
+                                                VoxelOf voxel_of, Done done, uint32_t &val,
+                                                Decision dec = Decision{}) {
     const uint32_t D = v.D;
     const double cr = v.cr, ci = v.ci;
     const bool special = !(cr * cr + ci * ci <= 3.99);  // the same for every voxel
@@ -174,10 +183,11 @@ __device__ __forceinline__ uint32_t quat_stream(const Vol3 &v, uint32_t n_surf, 
         // voxel still running (k >= 1) or a v above 1 shows a mixed surface.
         if (kSurface && scanning && __ballot(ones)) {
             if (!vset) {
-                val = 1;
+                val = dec.propose(1u);
                 vset = true;
             }
             if (val != 1 || __ballot(have)) {
+                dec.set_mixed();
                 if (n_all == n_surf)
                     return 1;
                 scanning = false;
@@ -240,15 +250,18 @@ __device__ __forceinline__ uint32_t quat_stream(const Vol3 &v, uint32_t n_surf, 
             }
         }
         if (kSurface && scanning) {
+            if (!vset && dec.known(val))
+                vset = true;
             if (!vset && __ballot(fin)) {
                 uint32_t m = fin ? dw : 0xffffffffu;
 #pragma unroll
                 for (int o = 32; o > 0; o >>= 1)
                     m = min(m, (uint32_t)__shfl_xor((unsigned int)m, o));
-                val = __builtin_amdgcn_readfirstlane(m);
+                val = dec.propose(__builtin_amdgcn_readfirstlane(m));
                 vset = true;
             }
-            if (vset && __ballot((fin && dw != val) || (have && k >= val))) {
+            if ((vset && __ballot((fin && dw != val) || (have && k >= val))) || dec.mixed()) {
+                dec.set_mixed();
                 if (n_all == n_surf)
                     return 1;
                 scanning = false;
@@ -486,7 +499,7 @@ struct Div {
 // Voxel t of the surface of a w x h x l box: the two z faces, then the
 // rectangular ring of each inner slice. A box with a side of 1 or 2 is all
 // surface and is walked in storage order.
-__device__ __forceinline__ uint32_t surface_count(uint32_t w, uint32_t h, uint32_t l) {
+__host__ __device__ __forceinline__ uint32_t surface_count(uint32_t w, uint32_t h, uint32_t l) {
     if (w <= 2 || h <= 2 || l <= 2)
         return w * h * l;
     return 2 * w * h + (l - 2) * (2 * w + 2 * (h - 2));
@@ -531,16 +544,17 @@ struct Surface {
     }
 };
 
-// T: every voxel of the box (lo, w x h x l) takes dwell d. With w <= 64 the
-// lanes hold a column x each and walk rows (y fastest, then z) 64 / w
-// rows apart, so no voxel needs a division.
+// T: every voxel of the box (lo, w x h x l) takes dwell d, written by part
+// `part` of `parts` waves. With w <= 64 the lanes hold a column x each and
+// walk rows (y fastest, then z) 64 / w rows apart per wave, so no voxel
+// needs a division.
 __device__ void fill_box(const Vol3 &v, const uint32_t lo[3], uint32_t w, uint32_t h,
-                         uint32_t l, uint32_t d, uint32_t lane) {
+                         uint32_t l, uint32_t d, uint32_t lane, uint32_t part = 0,
+                         uint32_t parts = 1) {
     if (w > kLanes) {
-        for (uint32_t z = 0; z < l; ++z)
-            for (uint32_t y = 0; y < h; ++y)
-                for (uint32_t x = lane; x < w; x += kLanes)
-                    put_voxel(v, lo[0] + x, lo[1] + y, lo[2] + z, d);
+        for (uint32_t r = part; r < h * l; r += parts)
+            for (uint32_t x = lane; x < w; x += kLanes)
+                put_voxel(v, lo[0] + x, lo[1] + r % h, lo[2] + r / h, d);
         return;
     }
     const uint32_t rows = kLanes / w;
@@ -548,13 +562,14 @@ __device__ void fill_box(const Vol3 &v, const uint32_t lo[3], uint32_t w, uint32
     uint32_t y = lane / w, z = 0;
     if (y >= rows)
         return;
+    y += part * rows;
     while (y >= h) {
         y -= h;
         ++z;
     }
     while (z < l) {
         put_voxel(v, lo[0] + x, lo[1] + y, lo[2] + z, d);
-        y += rows;
+        y += rows * parts;
         while (y >= h) {
             y -= h;
             ++z;
@@ -562,8 +577,111 @@ __device__ void fill_box(const Vol3 &v, const uint32_t lo[3], uint32_t w, uint32
     }
 }
 
+// A box of a level table, decoded, with its surface order: the surface in a
+// spread order, so that a mixed surface shows it early: A arcs of 2^bits
+// voxels (A between 64 and 128 once the surface has 64 voxels or more), one
+// voxel of every arc per round, at offsets taken in bit-reversed round order
+// (0, 1/2, 1/4, 3/4, ... of an arc), so that only the last arc's tail names
+// no voxel. Inside voxels are numbered in storage order.
+struct Box {
+    uint32_t p[3], lo[3];
+    uint32_t w, h, l, S, bits, arcs, n_surf, iw, ih, inside;
+    bool ok, leaf_size;
+    Surface surf;
+    Div darcs, diw, dih;
+
+    __device__ static Box decode(const Vol3 &v, const Level3 &L, uint64_t scalar) {
+        uint32_t p[3], lo[3], hi[3];
+        scalar_cell(scalar, L.G, L.curve, p);
+        const bool ok = cell_box(v, L.G, p, lo, hi);
+        return Box(p, lo, ok ? hi[0] - lo[0] : 1u, ok ? hi[1] - lo[1] : 1u,
+                   ok ? hi[2] - lo[2] : 1u, ok, L.B);
+    }
+
+    __device__ Box(const uint32_t p_[3], const uint32_t lo_[3], uint32_t w_, uint32_t h_,
+                   uint32_t l_, bool ok_, uint32_t B)
+        : w(w_), h(h_), l(l_), S(surface_count(w_, h_, l_)),
+          bits(S >= 2 * kLanes ? 31u - (uint32_t)__builtin_clz(S / kLanes) : 0u),
+          arcs((S + (1u << bits) - 1) >> bits), n_surf(arcs << bits),
+          iw(w_ <= 2 || h_ <= 2 || l_ <= 2 ? 1u : w_ - 2),
+          ih(w_ <= 2 || h_ <= 2 || l_ <= 2 ? 1u : h_ - 2),
+          inside(w_ <= 2 || h_ <= 2 || l_ <= 2 ? 0u : (w_ - 2) * (h_ - 2) * (l_ - 2)), ok(ok_),
+          leaf_size(w_ <= B && h_ <= B && l_ <= B), surf(w_, h_, l_), darcs(arcs), diw(iw),
+          dih(ih) {
+        for (int d = 0; d < 3; ++d) {
+            p[d] = p_[d];
+            lo[d] = lo_[d];
+        }
+    }
+
+    // Surface position j of the spread order; false when it names no voxel.
+    __device__ __forceinline__ bool surface_at(uint32_t j, uint32_t &x, uint32_t &y,
+                                               uint32_t &z) const {
+        const uint32_t round = darcs.div(j);
+        const uint32_t off = bits ? __brev(round) >> (32u - bits) : 0u;
+        const uint32_t t = ((j - round * arcs) << bits) + off;
+        if (t >= S)
+            return false;
+        surf.voxel(t, x, y, z);
+        x += lo[0];
+        y += lo[1];
+        z += lo[2];
+        return true;
+    }
+
+    // Inside voxel t (t < inside).
+    __device__ __forceinline__ void inside_at(uint32_t t, uint32_t &x, uint32_t &y,
+                                              uint32_t &z) const {
+        const uint32_t row = diw.div(t), zi = dih.div(row);
+        x = lo[0] + 1 + (t - row * iw);
+        y = lo[1] + 1 + (row - zi * ih);
+        z = lo[2] + 1 + zi;
+    }
+};
+
+// S: the non-empty children of box p go to the next level's table, one
+// ballot and one atomic add per 64 children.
+__device__ void emit_children(const Vol3 &v, const Level3 &L, const uint32_t p[3], uint32_t lane) {
+    const uint32_t r = L.r, kids = r * r * r;
+    const uint64_t G1 = L.G * r;
+    for (uint32_t k0 = 0; k0 < kids; k0 += kLanes) {
+        const uint32_t k = k0 + lane;
+        uint32_t c[3] = {0, 0, 0}, clo[3], chi[3];
+        bool ok = false;
+        if (k < kids) {
+            c[0] = p[0] * r + k % r;
+            c[1] = p[1] * r + (k / r) % r;
+            c[2] = p[2] * r + k / (r * r);
+            ok = cell_box(v, G1, c, clo, chi);
+        }
+        const uint64_t mask = __ballot(ok);
+        const uint64_t base = wave_base(&L.ctrl[kCountW + L.level + 1], mask, lane);
+        if (ok) {
+            const uint64_t at = base + lanes_below(mask, lane);
+            if (at < L.cap)
+                L.next[at] = cell_scalar(c, G1, L.curve);
+            else
+                atomicOr(&L.ctrl[kOverW], 1ull);
+        }
+    }
+}
+
+__device__ __forceinline__ void count_outcomes(const Level3 &L, unsigned long long nfill,
+                                               unsigned long long nsplit,
+                                               unsigned long long nleaf) {
+    if (nfill)
+        atomicAdd(&L.ctrl[kFillW + L.level], nfill);
+    if (nsplit)
+        atomicAdd(&L.ctrl[kSplitW + L.level], nsplit);
+    if (nleaf)
+        atomicAdd(&L.ctrl[kLeafW + L.level], nleaf);
+}
+
 // One level: each wave takes boxes from the level's table and decides them
 // (surface uniform -> fill; every side <= B -> every voxel; else split).
+// Every finished surface dwell is written: whatever follows, a voxel on a
+// scanned surface ends with its own dwell, so a leaf box's stream goes on
+// from its surface into its inside.
 __global__ __launch_bounds__(kThreads) void level3_kernel(Vol3 v, Level3 L) {
     const uint32_t lane = threadIdx.x & (kLanes - 1);
     const uint64_t count = std::min((uint64_t)L.ctrl[kCountW + L.level], L.cap);
@@ -575,99 +693,153 @@ __global__ __launch_bounds__(kThreads) void level3_kernel(Vol3 v, Level3 L) {
     unsigned long long nfill = 0, nsplit = 0, nleaf = 0;
     claim_items(&L.ctrl[kClaimW + L.level * kXcds * kLineWords], kLineWords, count, chunk,
                 [&](uint64_t e) {
-        uint32_t p[3], lo[3], hi[3];
-        scalar_cell(uniform64_3(L.in[e]), L.G, L.curve, p);  // wave-uniform box
-        if (!cell_box(v, L.G, p, lo, hi)) {
+        const Box bx = Box::decode(v, L, uniform64_3(L.in[e]));  // wave-uniform box
+        if (!bx.ok) {
             if (lane == 0)
                 atomicOr(&L.ctrl[kOverW], 2ull);
             return;
         }
-        const uint32_t w = hi[0] - lo[0], h = hi[1] - lo[1], l = hi[2] - lo[2];
-        const uint32_t S = surface_count(w, h, l);
-        const bool leaf_size = w <= L.B && h <= L.B && l <= L.B;
-        // The surface in a spread order, so that a mixed surface shows it
-        // early: A arcs of 2^bits voxels (A between 64 and 128 once the
-        // surface has 64 voxels or more), one voxel of every arc per round,
-        // at offsets taken in bit-reversed round order (0, 1/2, 1/4, 3/4,
-        // ... of an arc), so that only the last arc's tail names no voxel.
-        // A leaf box's stream goes on into its inside. Every finished
-        // surface dwell is written: whatever follows, a voxel on a scanned
-        // surface ends with its own dwell.
-        const uint32_t bits = S >= 2 * kLanes ? 31u - (uint32_t)__builtin_clz(S / kLanes) : 0u;
-        const uint32_t arcs = (S + (1u << bits) - 1) >> bits;
-        const Div darcs(arcs);
-        const uint32_t n_surf = arcs << bits;
-        const bool thin = w <= 2 || h <= 2 || l <= 2;
-        const uint32_t iw = thin ? 1u : w - 2, ih = thin ? 1u : h - 2;
-        const uint32_t inside = thin ? 0u : iw * ih * (l - 2);
-        const Surface surf(w, h, l);
-        const Div diw(iw), dih(ih);
         uint32_t first = 0;
         const uint32_t outcome = quat_stream<true>(
-            v, n_surf, leaf_size ? n_surf + inside + 1u : n_surf,
+            v, bx.n_surf, bx.leaf_size ? bx.n_surf + bx.inside + 1u : bx.n_surf,
             [&](uint32_t j, uint32_t &x, uint32_t &y, uint32_t &z) {
-                if (j >= n_surf) {
-                    const uint32_t t = j - n_surf;
-                    if (t >= inside)
-                        return false;
-                    const uint32_t row = diw.div(t), zi = dih.div(row);
-                    x = lo[0] + 1 + (t - row * iw);
-                    y = lo[1] + 1 + (row - zi * ih);
-                    z = lo[2] + 1 + zi;
-                    return true;
-                }
-                const uint32_t round = darcs.div(j);
-                const uint32_t off = bits ? __brev(round) >> (32u - bits) : 0u;
-                const uint32_t t = ((j - round * arcs) << bits) + off;
-                if (t >= S)
+                if (j < bx.n_surf)
+                    return bx.surface_at(j, x, y, z);
+                if (j - bx.n_surf >= bx.inside)
                     return false;
-                surf.voxel(t, x, y, z);
-                x += lo[0];
-                y += lo[1];
-                z += lo[2];
+                bx.inside_at(j - bx.n_surf, x, y, z);
                 return true;
             },
             [&](uint32_t x, uint32_t y, uint32_t z, uint32_t d, bool) { put_voxel(v, x, y, z, d); },
             first);
         if (outcome == 0) {
-            fill_box(v, lo, w, h, l, first, lane);
+            fill_box(v, bx.lo, bx.w, bx.h, bx.l, first, lane);
             ++nfill;
-        } else if (leaf_size) {
+        } else if (bx.leaf_size) {
             ++nleaf;
         } else {
-            const uint32_t r = L.r, kids = r * r * r;
-            const uint64_t G1 = L.G * r;
-            for (uint32_t k0 = 0; k0 < kids; k0 += kLanes) {
-                const uint32_t k = k0 + lane;
-                uint32_t c[3] = {0, 0, 0}, clo[3], chi[3];
-                bool ok = false;
-                if (k < kids) {
-                    c[0] = p[0] * r + k % r;
-                    c[1] = p[1] * r + (k / r) % r;
-                    c[2] = p[2] * r + k / (r * r);
-                    ok = cell_box(v, G1, c, clo, chi);
-                }
-                const uint64_t mask = __ballot(ok);
-                const uint64_t base = wave_base(&L.ctrl[kCountW + L.level + 1], mask, lane);
-                if (ok) {
-                    const uint64_t at = base + lanes_below(mask, lane);
-                    if (at < L.cap)
-                        L.next[at] = cell_scalar(c, G1, L.curve);
-                    else
-                        atomicOr(&L.ctrl[kOverW], 1ull);
-                }
-            }
+            emit_children(v, L, bx.p, lane);
             ++nsplit;
         }
     });
-    if (lane == 0) {
-        if (nfill)
-            atomicAdd(&L.ctrl[kFillW + L.level], nfill);
-        if (nsplit)
-            atomicAdd(&L.ctrl[kSplitW + L.level], nsplit);
-        if (nleaf)
-            atomicAdd(&L.ctrl[kLeafW + L.level], nleaf);
+    if (lane == 0)
+        count_outcomes(L, nfill, nsplit, nleaf);
+}
+
+// The surface decision of a workgroup's waves sharing one box, in LDS: the
+// first dwell proposed becomes v for all, and any wave that sees the surface
+// mixed says so to the others.
+constexpr uint32_t kNoVal = 0xffffffffu;
+
+struct SharedDecision {
+    uint32_t *val, *flag;
+    __device__ uint32_t propose(uint32_t x) const {
+        uint32_t old = kNoVal;
+        if (first_lane3())
+            old = atomicCAS(val, kNoVal, x);
+        old = __builtin_amdgcn_readfirstlane(old);
+        return old == kNoVal ? x : old;
     }
+    __device__ bool known(uint32_t &x) const {
+        const uint32_t y = __builtin_amdgcn_readfirstlane(*(volatile uint32_t *)val);
+        if (y == kNoVal)
+            return false;
+        x = y;
+        return true;
+    }
+    __device__ bool mixed() const {
+        return __builtin_amdgcn_readfirstlane(*(volatile uint32_t *)flag) != 0;
+    }
+    __device__ void set_mixed() const {
+        if (first_lane3())
+            *(volatile uint32_t *)flag = 1u;
+    }
+};
+
+// Levels of large boxes (kCoopSurface surface voxels or more): the four
+// waves of a workgroup share one box. Each scans every fourth position of
+// the surface order, and they decide the surface together through LDS (a
+// mixed one stops every wave at its next round); then they fill the box
+// together, stream a leaf box's inside together (the surface of a leaf box
+// is always scanned whole), or one wave appends the children. A box's
+// critical path is a quarter of one wave's.
+constexpr uint32_t kCoopSurface = 1024;
+
+__global__ __launch_bounds__(kThreads) void level3_coop_kernel(Vol3 v, Level3 L) {
+    __shared__ unsigned long long sh_e;
+    __shared__ uint32_t sh_val, sh_mixed;
+    const uint32_t lane = threadIdx.x & (kLanes - 1), wave = threadIdx.x / kLanes;
+    const uint64_t count = std::min((uint64_t)L.ctrl[kCountW + L.level], L.cap);
+    unsigned long long *counters = &L.ctrl[kClaimW + L.level * kXcds * kLineWords];
+    const SharedDecision dec{&sh_val, &sh_mixed};
+    const uint32_t home = xcd_id();
+    uint32_t q = 0;  // thread 0: the counter it claims from (home, then the others)
+    unsigned long long nfill = 0, nsplit = 0, nleaf = 0;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            unsigned long long e = ~0ull;
+            while (q < kXcds) {
+                const uint32_t x = (home + q) & (kXcds - 1);
+                const uint64_t mine = count > x ? (count - x + kXcds - 1) / kXcds : 0;
+                const uint64_t k = atomicAdd(&counters[x * kLineWords], 1ull);
+                if (k < mine) {
+                    e = x + k * kXcds;
+                    break;
+                }
+                ++q;
+            }
+            sh_e = e;
+            sh_val = kNoVal;
+            sh_mixed = 0;
+        }
+        __syncthreads();
+        const uint64_t e = uniform64_3(*(volatile unsigned long long *)&sh_e);
+        if (e == ~0ull)
+            break;
+        const Box bx = Box::decode(v, L, uniform64_3(L.in[e]));
+        if (bx.ok) {
+            const uint32_t part = bx.n_surf > wave ? (bx.n_surf - wave + kWavesPer - 1) / kWavesPer : 0u;
+            uint32_t vloc = 0;
+            quat_stream<true>(
+                v, part, bx.leaf_size ? part + 1u : part,
+                [&](uint32_t i, uint32_t &x, uint32_t &y, uint32_t &z) {
+                    return i < part && bx.surface_at(wave + i * kWavesPer, x, y, z);
+                },
+                [&](uint32_t x, uint32_t y, uint32_t z, uint32_t d, bool) { put_voxel(v, x, y, z, d); },
+                vloc, dec);
+        } else if (threadIdx.x == 0) {
+            atomicOr(&L.ctrl[kOverW], 2ull);
+        }
+        __syncthreads();
+        if (bx.ok) {
+            const bool mixed = dec.mixed();
+            uint32_t val = 0;
+            dec.known(val);
+            if (!mixed) {
+                fill_box(v, bx.lo, bx.w, bx.h, bx.l, val, lane, wave, kWavesPer);
+                ++nfill;
+            } else if (bx.leaf_size) {
+                const uint32_t part = bx.inside > wave ? (bx.inside - wave + kWavesPer - 1) / kWavesPer : 0u;
+                uint32_t none = 0;
+                quat_stream<false>(
+                    v, 0u, part,
+                    [&](uint32_t i, uint32_t &x, uint32_t &y, uint32_t &z) {
+                        bx.inside_at(wave + i * kWavesPer, x, y, z);
+                        return true;
+                    },
+                    [&](uint32_t x, uint32_t y, uint32_t z, uint32_t d, bool) { put_voxel(v, x, y, z, d); },
+                    none);
+                ++nleaf;
+            } else {
+                if (wave == 0)
+                    emit_children(v, L, bx.p, lane);
+                ++nsplit;
+            }
+        }
+        __syncthreads();  // the LDS words are the next box's
+    }
+    if (threadIdx.x == 0)
+        count_outcomes(L, nfill, nsplit, nleaf);
 }
 
 // ---------------------------------------------------------------------------
@@ -804,11 +976,17 @@ extern "C" ask_status ask3_dwell_subdiv(const ask_volume *v, const ask3_params *
         return ASK_EDEVICE;
     // The level kernel's resident workgroups per CU: a grid larger than the
     // device holds at once would leave workgroups waiting for others to end.
-    int occ = 0;
+    int occ = 0, occ_coop = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, level3_kernel, kThreads, 0) != hipSuccess ||
         occ < 1) {
         (void)hipGetLastError();
         occ = 1;
+    }
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_coop, level3_coop_kernel, kThreads, 0) !=
+            hipSuccess ||
+        occ_coop < 1) {
+        (void)hipGetLastError();
+        occ_coop = 1;
     }
     const uint64_t cap = table_cap(v, p);
     const uint32_t levels = reachable_levels(v, p);
@@ -837,9 +1015,19 @@ extern "C" ask_status ask3_dwell_subdiv(const ask_volume *v, const ask3_params *
         L.curve = p->curve;
         L.level = i;
         const uint64_t bound = i == 0 ? level0 : cap;
-        const uint32_t blocks = (uint32_t)std::max<uint64_t>(
-            1, std::min<uint64_t>((bound + kWavesPer - 1) / kWavesPer, (uint64_t)cus * occ));
-        hipLaunchKernelGGL(level3_kernel, dim3(blocks), dim3(kThreads), 0, s, vol, L);
+        // The level's largest box: sides ceil(n / G) (floor partition).
+        const uint32_t S_max = surface_count((uint32_t)((v->W + G - 1) / G),
+                                             (uint32_t)((v->H + G - 1) / G),
+                                             (uint32_t)((v->L + G - 1) / G));
+        if (S_max >= kCoopSurface) {
+            const uint32_t blocks = (uint32_t)std::max<uint64_t>(
+                1, std::min<uint64_t>(bound, (uint64_t)cus * occ_coop));
+            hipLaunchKernelGGL(level3_coop_kernel, dim3(blocks), dim3(kThreads), 0, s, vol, L);
+        } else {
+            const uint32_t blocks = (uint32_t)std::max<uint64_t>(
+                1, std::min<uint64_t>((bound + kWavesPer - 1) / kWavesPer, (uint64_t)cus * occ));
+            hipLaunchKernelGGL(level3_kernel, dim3(blocks), dim3(kThreads), 0, s, vol, L);
+        }
     }
     ask_status st = launched();
     if (st != ASK_OK || !stats)

@@ -28,6 +28,13 @@ VOLUMES = [
     (Volume(-1.4, 1.4, -1.3, 1.3, -0.7, 0.7, 70, 66, 35, 3000, c=(-0.125, 0.65)), 4, 2, 5),
     # c beyond |c| = 2: every orbit escapes at once or never starts close
     (Volume(-2.5, 2.5, -2.5, 2.5, -2.5, 2.5, 33, 30, 27, 100, c=(2.1, 0.3)), 3, 2, 4),
+    # boxes whose surface a whole workgroup scans: 32^3 boxes split into 16^3
+    # leaf boxes; ragged 44 x 32 x 25 boxes and their leaf children; thin
+    # 50 x 45 x 2 leaf boxes (all surface); |c| > 2 on 30^3 leaf boxes
+    (Volume(-1.6, 1.6, -1.6, 1.6, -1.6, 1.6, 96, 96, 96, 256, c=(-0.2, 0.6)), 3, 2, 16),
+    (Volume(-1.3, 1.1, -1.2, 1.2, -1.1, 1.3, 131, 97, 75, 256, c=(-0.2, 0.6)), 3, 2, 24),
+    (Volume(-1.5, 1.5, -1.5, 1.5, -0.02, 0.02, 100, 90, 2, 300, c=(-1.0, 0.0)), 2, 2, 64),
+    (Volume(-2.5, 2.5, -2.5, 2.5, -2.5, 2.5, 60, 60, 60, 100, c=(2.1, 0.3)), 2, 2, 30),
 ]
 
 

@@ -175,11 +175,11 @@ class Volume:
 
 # The 3-D workload: 512^3 voxels over [-1.6, 1.6]^3, dwell limit 256, for a c
 # off the real axis (no rotational symmetry; 8 % of the voxels reach D), with
-# a level-0 grid of 64^3 boxes of 8^3 voxels, r = 2, B = 8 (one level): the
-# fastest of the sweep `python -m paper_2206_02255_amd.autotune --volume`.
+# a level-0 grid of 32^3 boxes of 16^3 voxels, r = 2, B = 8: the fastest of
+# the sweep `python -m paper_2206_02255_amd.autotune --volume`.
 VOLUME_C = (-0.2, 0.6)
 VOLUME = Volume(-1.6, 1.6, -1.6, 1.6, -1.6, 1.6, 512, 512, 512, 256, c=VOLUME_C)
-VOLUME_PARAMS = Params(64, 2, 8)
+VOLUME_PARAMS = Params(32, 2, 8)
 
 
 def rule_params(side, s0, r, B):
