@@ -552,6 +552,21 @@ hipError_t upload_words(uint32_t *dst, const uint32_t *words, size_t n, hipStrea
     return hipSuccess;
 }
 
+// The longest ring of level lv over the images: regions of the floor
+// partition into g r^lv parts per axis are at most ceil(W / (g r^lv)) wide.
+uint32_t largest_ring(const Image *ims, uint32_t n, uint32_t lv) {
+    uint64_t best = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        uint64_t parts = ims[i].g;
+        for (uint32_t k = 0; k < lv && parts < (1ull << 32); ++k)
+            parts *= ims[i].r;
+        const uint64_t w = (ims[i].W + parts - 1) / parts, h = (ims[i].H + parts - 1) / parts;
+        const uint64_t ring = (w <= 1 || h <= 1) ? w * h : 2 * (w + h) - 4;
+        best = std::max(best, ring);
+    }
+    return (uint32_t)std::min<uint64_t>(best, 0xffffffffu);
+}
+
 // The launch sequence of a render: counters reset, level-0 seeding of every
 // image, then the persistent kernel over one queue or one kernel per level.
 // ctx (may be nullptr) records the timing events and read-back errors.
@@ -615,9 +630,14 @@ ask_status launch_render(ask_ctx *ctx, const Plan &p, const Buffers &bf, const I
             e = launch_level_exact(a, cnt, s);
         } else {
             const uint64_t entries = p.b.level[lv] + (lv > 0 ? p.band_bound : 0);
-            const uint64_t blocks =
-                std::min<uint64_t>(bf.resident_level, (entries + kWavesPerBlock - 1) / kWavesPerBlock);
-            e = launch_level(a, (uint32_t)std::max<uint64_t>(1, blocks), s);
+            if (largest_ring(ims, n, lv) >= kCoopRingPixels) {
+                const uint64_t blocks = std::min<uint64_t>(bf.resident_level, entries);
+                e = launch_level_coop(a, (uint32_t)std::max<uint64_t>(1, blocks), s);
+            } else {
+                const uint64_t blocks = std::min<uint64_t>(
+                    bf.resident_level, (entries + kWavesPerBlock - 1) / kWavesPerBlock);
+                e = launch_level(a, (uint32_t)std::max<uint64_t>(1, blocks), s);
+            }
         }
         if (e != hipSuccess)
             return hip_fail(ctx, e, "level kernel launch");

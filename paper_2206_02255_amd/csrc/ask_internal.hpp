@@ -182,6 +182,9 @@ hipError_t launch_clear_queue(Region *queue, uint32_t entries, hipStream_t s);
 hipError_t launch_seed_levels(const SubdivArgs &a, uint32_t nseeds, hipStream_t s);
 hipError_t launch_seed_queue(const SubdivArgs &a, uint32_t nseeds, hipStream_t s);
 hipError_t launch_level(const SubdivArgs &a, uint32_t grid_blocks, hipStream_t s);
+// Per-level kernel with a workgroup per region, for levels of large regions.
+hipError_t launch_level_coop(const SubdivArgs &a, uint32_t grid_blocks, hipStream_t s);
+constexpr uint32_t kCoopRingPixels = 512;  // rings of this many pixels or more
 hipError_t launch_level_exact(const SubdivArgs &a, uint32_t nregions, hipStream_t s);
 hipError_t launch_persistent(const SubdivArgs &a, uint32_t grid_blocks, hipStream_t s);
 hipError_t occupancy_level(int *blocks_per_cu);

@@ -255,10 +255,18 @@ constexpr uint32_t kRoundBlocks = 4;
 
 enum StreamEnd : uint32_t { kUniform = 0, kMixed = 1, kLeafDone = 2 };
 
-template <bool kRing, class PixelOf, class Done>
+// The ring decision of one wave alone: v is the wave's own.
+struct SoloDecision {
+    __device__ uint32_t propose(uint32_t x) const { return x; }
+    __device__ bool known(uint32_t &) const { return false; }
+    __device__ bool mixed() const { return false; }
+    __device__ void set_mixed() const {}
+};
+
+template <bool kRing, class PixelOf, class Done, class Decision = SoloDecision>
 __device__ __forceinline__ uint32_t dwell_stream(const Image &im, uint32_t n_ring, uint32_t n_all,
                                                  PixelOf pixel_of, Done done, uint32_t &v,
-                                                 uint32_t &partial) {
+                                                 uint32_t &partial, Decision dec = Decision{}) {
     const uint32_t D = im.D;
     uint32_t next = 0;  // first stream index no lane has taken yet (uniform)
     uint32_t n = kRing ? n_ring : n_all;  // end of the stream as far as it is known to run
@@ -354,11 +362,14 @@ __device__ __forceinline__ uint32_t dwell_stream(const Image &im, uint32_t n_rin
             }
         }
         if (kRing && scanning) {
+            if (!vset && dec.known(v))
+                vset = true;
             if (!vset && __ballot(fin)) {
-                v = uniform(wave_min(fin ? dw : 0xffffffffu));
+                v = dec.propose(uniform(wave_min(fin ? dw : 0xffffffffu)));
                 vset = true;
             }
-            if (vset && __ballot((fin && dw != v) || (have && kbase >= v))) {
+            if ((vset && __ballot((fin && dw != v) || (have && kbase >= v))) || dec.mixed()) {
+                dec.set_mixed();
                 if (n_all == n_ring) {
                     partial = have ? kbase : 0u;
                     return kMixed;
@@ -412,9 +423,10 @@ __device__ __forceinline__ uint32_t ring_size(uint32_t w, uint32_t h) {
 // Terminal work T: write v on every pixel of the region. Rows of 64 or more
 // pixels are written row by row, narrower regions several rows per pass.
 __device__ void fill_region(uint32_t *out, uint32_t W, uint32_t x, uint32_t y, uint32_t w,
-                            uint32_t h, uint32_t v, uint32_t lane) {
+                            uint32_t h, uint32_t v, uint32_t lane, uint32_t part = 0,
+                            uint32_t parts = 1) {
     if (w >= kWave) {
-        for (uint32_t row = 0; row < h; ++row) {
+        for (uint32_t row = part; row < h; row += parts) {
             uint32_t *p = out + (size_t)(y + row) * W + x;
             for (uint32_t c = lane; c < w; c += kWave)
                 put_dwell(p, c, v);
@@ -423,7 +435,7 @@ __device__ void fill_region(uint32_t *out, uint32_t W, uint32_t x, uint32_t y, u
         const uint32_t per = kWave / w;
         const uint32_t lr = lane / w, lc = lane - lr * w;
         if (lr < per)
-            for (uint32_t row = lr; row < h; row += per)
+            for (uint32_t row = lr + part * per; row < h; row += per * parts)
                 put_dwell(out, (size_t)(y + row) * W + x + lc, v);
     }
 }
@@ -634,6 +646,35 @@ __device__ void decide_region(const SubdivArgs &a, uint32_t img, const Image &im
         wave_add64(&st->splits[level], 1ull);
 }
 
+// The positions of a ring scan: the ring in its spread order (n_ring
+// positions), then, for a leaf, its inside (RectOrder).
+struct RingLeafOrder {
+    uint32_t x, y, w, h, nring, q, bits, n_ring, n_all;
+    RectOrder order;
+    __device__ RingLeafOrder(const Image &im, uint32_t x_, uint32_t y_, uint32_t w_, uint32_t h_,
+                             bool leaf)
+        : x(x_), y(y_), w(w_), h(h_), nring(ring_size(w_, h_)), q((nring + kWave - 1) / kWave),
+          bits(q > 1 ? 32u - (uint32_t)__builtin_clz(q - 1) : 0u),  // 2^bits >= q
+          n_ring(kWave << bits), n_all(0),
+          order(im, x_ + 1, y_ + 1, leaf && w_ > 2 && h_ > 2 ? w_ - 2 : 1u,
+                leaf && w_ > 2 && h_ > 2 ? h_ - 2 : 1u) {
+        n_all = n_ring + (leaf && w_ > 2 && h_ > 2 ? order.positions() : 0u);
+    }
+    // The stream's end: a leaf's stream runs past the ring even with no inside.
+    __device__ uint32_t end(bool leaf) const { return leaf ? max(n_all, n_ring + 1u) : n_ring; }
+    __device__ __forceinline__ bool pixel(uint32_t j, uint32_t &px, uint32_t &py) const {
+        if (j >= n_ring)
+            return j < n_all && order.pixel(j - n_ring, px, py);
+        const uint32_t round = j / kWave;
+        const uint32_t off = bits ? __brev(round) >> (32u - bits) : 0u;
+        const uint32_t t = (j % kWave) * q + off;
+        if (off >= q || t >= nring)
+            return false;
+        ring_pixel(x, y, w, h, t, px, py);
+        return true;
+    }
+};
+
 // Q over the whole ring, taken in a spread order. The ring is cut into 64
 // arcs of q pixels, one per lane of the first round, so the first 64 pixels
 // are spaced evenly around it; later rounds take, in every arc, the offsets
@@ -654,28 +695,12 @@ __device__ void decide_region(const SubdivArgs &a, uint32_t img, const Image &im
 // counters: ring pixels to the ring's, inside pixels to the leaves'.
 __device__ uint32_t scan_ring(const SubdivArgs &a, const Image &im, uint32_t x, uint32_t y,
                               uint32_t w, uint32_t h, bool leaf, uint32_t &v) {
-    const uint32_t nring = ring_size(w, h);
-    const uint32_t q = (nring + kWave - 1) / kWave;
-    const uint32_t bits = q > 1 ? 32u - (uint32_t)__builtin_clz(q - 1) : 0u;  // 2^bits >= q
-    const uint32_t n_ring = kWave << bits;
-    const bool inside = leaf && w > 2 && h > 2;
-    const RectOrder order(im, x + 1, y + 1, inside ? w - 2 : 1u, inside ? h - 2 : 1u);
-    const uint32_t n_all = n_ring + (inside ? order.positions() : 0u);
+    const RingLeafOrder ro(im, x, y, w, h, leaf);
     unsigned long long it_ring = 0, it_leaf = 0;
     uint32_t partial = 0;
     const uint32_t outcome = dwell_stream<true>(
-        im, n_ring, leaf ? max(n_all, n_ring + 1u) : n_ring,
-        [&](uint32_t j, uint32_t &px, uint32_t &py) {
-            if (j >= n_ring)
-                return j < n_all && order.pixel(j - n_ring, px, py);
-            const uint32_t round = j / kWave;
-            const uint32_t off = bits ? __brev(round) >> (32u - bits) : 0u;
-            const uint32_t t = (j % kWave) * q + off;
-            if (off >= q || t >= nring)
-                return false;
-            ring_pixel(x, y, w, h, t, px, py);
-            return true;
-        },
+        im, ro.n_ring, ro.end(leaf),
+        [&](uint32_t j, uint32_t &px, uint32_t &py) { return ro.pixel(j, px, py); },
         [&](uint32_t px, uint32_t py, uint32_t d, bool ring) {
             put_dwell(im.out, (size_t)py * im.W + px, d);
             if (ring)
@@ -744,6 +769,148 @@ __global__ __launch_bounds__(kBlock) void level_exact_kernel(SubdivArgs a, uint3
     if (idx >= n)
         return;
     process_region<false>(a, a.in[idx], lane);
+}
+
+// The ring decision of a workgroup's waves sharing one region, in LDS: the
+// first dwell proposed becomes v for all, and a wave that sees the ring
+// mixed says so to the others.
+constexpr uint32_t kNoVal = 0xffffffffu;
+
+struct SharedDecision {
+    uint32_t *val, *flag;
+    __device__ uint32_t propose(uint32_t x) const {
+        uint32_t old = kNoVal;
+        if (first_lane())
+            old = atomicCAS(val, kNoVal, x);
+        old = uniform(old);
+        return old == kNoVal ? x : old;
+    }
+    __device__ bool known(uint32_t &x) const {
+        const uint32_t y = uniform(*(volatile uint32_t *)val);
+        if (y == kNoVal)
+            return false;
+        x = y;
+        return true;
+    }
+    __device__ bool mixed() const { return uniform(*(volatile uint32_t *)flag) != 0; }
+    __device__ void set_mixed() const {
+        if (first_lane())
+            *(volatile uint32_t *)flag = 1u;
+    }
+};
+
+// Per-level kernel for levels of large regions (rings of kCoopRingPixels
+// pixels or more): the four waves of a workgroup share one region. Each scans every
+// fourth position of the ring order and they decide the ring together
+// through LDS (a mixed ring stops every wave at its next round); after a
+// barrier they fill the region together, or stream a leaf's inside together
+// (a leaf's ring is always scanned whole), or one wave queues its bands or
+// appends its children. A long ring is then a quarter of a wave's work
+// instead of all of it.
+__global__ __launch_bounds__(kBlock) void level_coop_kernel(SubdivArgs a) {
+    __shared__ uint32_t sh_idx, sh_val, sh_mixed;
+    const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const uint32_t n = min(a.ctrl[kCount + a.level], a.cap);
+    const SharedDecision dec{&sh_val, &sh_mixed};
+    DevStats *st = a.stats;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            sh_idx = atomicAdd(&a.ctrl[kClaim + a.level], 1u);
+            sh_val = kNoVal;
+            sh_mixed = 0;
+        }
+        __syncthreads();
+        const uint32_t idx = uniform(*(volatile uint32_t *)&sh_idx);
+        if (idx >= n)
+            break;
+        const Region R = a.in[idx];
+        const uint32_t img = uniform(R.img), xy = uniform(R.xy), wh = uniform(R.wh);
+        const uint32_t tag = uniform(R.tag);
+        const uint32_t level = tag & 0x3fu, kind = (tag >> 6) & 0x3u;
+        const Image im = image_of(a, img);
+        const uint32_t x = xy & 0xffffu, y = xy >> 16;
+        const uint32_t w = (wh & 0xffffu) + 1, h = (wh >> 16) + 1;
+        const unsigned long long area = (unsigned long long)w * h;
+        const bool leaf_size = w <= im.B && h <= im.B;
+        const bool leaf = leaf_size && area <= im.band;
+        const RingLeafOrder ro(im, x, y, w, h, leaf);
+        if (kind == kLeaf) {  // a leaf band: one wave computes it
+            if (wave == 0) {
+                const unsigned long long li = leaf_region(im, x, y, w, h);
+                if (st)
+                    wave_add64(&st->iters_leaf, wave_sum(li));
+            }
+        } else {
+            const uint32_t part = ro.n_ring > wave ? (ro.n_ring - wave + kWavesPerBlock - 1) / kWavesPerBlock : 0u;
+            unsigned long long it_ring = 0;
+            uint32_t vloc = 0, partial = 0;
+            dwell_stream<true>(
+                im, part, leaf ? part + 1u : part,
+                [&](uint32_t i, uint32_t &px, uint32_t &py) {
+                    return i < part && ro.pixel(wave + i * kWavesPerBlock, px, py);
+                },
+                [&](uint32_t px, uint32_t py, uint32_t d, bool) {
+                    put_dwell(im.out, (size_t)py * im.W + px, d);
+                    it_ring += d;
+                },
+                vloc, partial, dec);
+            if (st)
+                wave_add64(&st->iters_ring, wave_sum(it_ring + partial));
+        }
+        __syncthreads();
+        if (kind != kLeaf) {
+            const bool mixed = dec.mixed();
+            uint32_t val = 0;
+            dec.known(val);
+            if (st && wave == 0) {
+                wave_add64(&st->regions[level], 1ull);
+                wave_add64(&st->ring_px, ring_size(w, h));
+                wave_max(&st->levels, level + 1);
+            }
+            if (!mixed) {
+                fill_region(im.out, im.W, x, y, w, h, val, lane, wave, kWavesPerBlock);
+                if (st && wave == 0) {
+                    wave_add64(&st->fills[level], 1ull);
+                    wave_add64(&st->fill_px, area);
+                }
+            } else if (leaf_size) {
+                if (st && wave == 0) {
+                    wave_add64(&st->leaves[level], 1ull);
+                    wave_add64(&st->leaf_px, area);
+                }
+                if (leaf) {
+                    const uint32_t np = w > 2 && h > 2 ? ro.order.positions() : 0u;
+                    const uint32_t part = np > wave ? (np - wave + kWavesPerBlock - 1) / kWavesPerBlock : 0u;
+                    unsigned long long it_leaf = 0;
+                    uint32_t vloc = 0, partial = 0;
+                    dwell_stream<false>(
+                        im, 0u, part,
+                        [&](uint32_t i, uint32_t &px, uint32_t &py) {
+                            return ro.order.pixel(wave + i * kWavesPerBlock, px, py);
+                        },
+                        [&](uint32_t px, uint32_t py, uint32_t d, bool) {
+                            put_dwell(im.out, (size_t)py * im.W + px, d);
+                            it_leaf += d;
+                        },
+                        vloc, partial);
+                    if (st)
+                        wave_add64(&st->iters_leaf, wave_sum(it_leaf));
+                } else if (wave == 0) {
+                    queue_leaf_bands<false>(a, img, x, y, w, h, im.band, level, lane);
+                }
+            } else if (wave == 0) {
+                if (level + 1 >= kMaxLevels) {
+                    wave_or(&a.ctrl[kOverflow], 2u);
+                    wave_or(&a.ctrl[kSticky], kErrOverflow);
+                } else {
+                    split_region<false>(a, img, x, y, w, h, im.r, level, lane);
+                    if (st)
+                        wave_add64(&st->splits[level], 1ull);
+                }
+            }
+        }
+        __syncthreads();  // the LDS words are the next region's
+    }
 }
 
 // Persistent kernel: every wave takes the next queue slot (one atomic add, a
@@ -1238,6 +1405,11 @@ hipError_t launch_seed_queue(const SubdivArgs &a, uint32_t nseeds, hipStream_t s
 
 hipError_t launch_level(const SubdivArgs &a, uint32_t grid_blocks, hipStream_t s) {
     hipLaunchKernelGGL(level_kernel, dim3(grid_blocks), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_level_coop(const SubdivArgs &a, uint32_t grid_blocks, hipStream_t s) {
+    hipLaunchKernelGGL(level_coop_kernel, dim3(grid_blocks), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
