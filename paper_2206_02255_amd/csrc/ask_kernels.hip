@@ -834,12 +834,24 @@ __global__ __launch_bounds__(kBlock) void level_coop_kernel(SubdivArgs a) {
         const bool leaf_size = w <= im.B && h <= im.B;
         const bool leaf = leaf_size && area <= im.band;
         const RingLeafOrder ro(im, x, y, w, h, leaf);
-        if (kind == kLeaf) {  // a leaf band: one wave computes it
-            if (wave == 0) {
-                const unsigned long long li = leaf_region(im, x, y, w, h);
-                if (st)
-                    wave_add64(&st->iters_leaf, wave_sum(li));
-            }
+        if (kind == kLeaf) {  // a leaf band: every fourth position on each wave
+            const RectOrder band(im, x, y, w, h);
+            const uint32_t np = band.positions();
+            const uint32_t part = np > wave ? (np - wave + kWavesPerBlock - 1) / kWavesPerBlock : 0u;
+            unsigned long long it_leaf = 0;
+            uint32_t vloc = 0, partial = 0;
+            dwell_stream<false>(
+                im, 0u, part,
+                [&](uint32_t i, uint32_t &px, uint32_t &py) {
+                    return band.pixel(wave + i * kWavesPerBlock, px, py);
+                },
+                [&](uint32_t px, uint32_t py, uint32_t d, bool) {
+                    put_dwell(im.out, (size_t)py * im.W + px, d);
+                    it_leaf += d;
+                },
+                vloc, partial);
+            if (st)
+                wave_add64(&st->iters_leaf, wave_sum(it_leaf));
         } else {
             const uint32_t part = ro.n_ring > wave ? (ro.n_ring - wave + kWavesPerBlock - 1) / kWavesPerBlock : 0u;
             unsigned long long it_ring = 0;

@@ -176,6 +176,27 @@ def test_subdiv_4096(gpu, ref, form, g, r, B):
     assert_same_stats(st, ref_st)
 
 
+# Levels whose rings have 512 pixels or more run a workgroup per region in
+# the per-level form: ragged regions that split, leaf-size regions whose
+# inside the four waves stream together (no bands), leaf-size regions cut
+# into bands, and a Julia set.
+WORKGROUP_CASES = [
+    (Window(-1.5, 0.5, -1.0, 1.0, 1500, 900, 600), 2, 2, 64, 0),
+    (Window(-1.5, 0.5, -1.0, 1.0, 1500, 900, 600), 2, 2, 800, 0xffffffff),
+    (Window(-1.5, 0.5, -1.0, 1.0, 1500, 900, 600), 2, 2, 800, 0),
+    (Window(-0.8, -0.6, 0.05, 0.2, 1111, 777, 1500), 1, 3, 40, 0),
+    (Window(-1.7, 1.7, -1.7, 1.7, 1200, 1200, 800, julia=(-1.0, 0.0)), 2, 4, 300, 0xffffffff),
+]
+
+
+@pytest.mark.parametrize("w,g,r,B,band", WORKGROUP_CASES)
+def test_levels_workgroup_regions(gpu, ref, w, g, r, B, band):
+    img, st = gpu_subdiv(gpu, w, g, r, B, "levels", band=band)
+    want, ref_st = ref.subdiv(w, g, r, B)
+    assert np.array_equal(img, want)
+    assert_same_stats(st, ref_st, no_bands=band == 0xffffffff)
+
+
 def test_subdiv_without_stats_equals_with_stats(gpu):
     w = paper_window(2048, 1024)
     for form in FORMS:
