@@ -76,7 +76,8 @@ __device__ __forceinline__ void put_voxel(const Vol3 &v, uint32_t x, uint32_t y,
 // idle. Here every lane iterates its own voxel, and after every stretch of
 // kStride3 iterations the lanes whose voxel has finished take the next
 // voxels of the stream. A lane takes a voxel with its first step done and
-// tested, and takes another at once when that voxel escaped there.
+// tested (a plain stream: its first two steps), and takes another at once
+// when that voxel escaped there.
 //
 // The dwell: q <- q^2 + c with q = a + b i + e j, c = cr + ci i, the first k
 // with |q_k|^2 > 4, else D; per step a' = (a^2 - (b^2 + e^2)) + cr,
@@ -172,6 +173,16 @@ __device__ __forceinline__ uint32_t quat_stream(const Vol3 &v, uint32_t n_surf, 
                         done(x, y, z, 1u, surf);
                         have = false;
                         ones = true;
+                    } else if (!kSurface && D > 1) {
+                        // A plain stream tests the second step here too: of
+                        // the voxels that survive the first, nearly half
+                        // escape at the second.
+                        quat_step(a, b, e, a2, s2, cr, ci);
+                        k = 2;
+                        if (a2 + s2 > 4.0) {
+                            done(x, y, z, 2u, surf);
+                            have = false;
+                        }
                     }
                 }
             }
