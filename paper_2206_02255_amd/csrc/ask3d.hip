@@ -75,9 +75,8 @@ __device__ __forceinline__ void put_voxel(const Vol3 &v, uint32_t x, uint32_t y,
 // gives each lane one voxel waits for its slowest voxel with most lanes
 // idle. Here every lane iterates its own voxel, and after every stretch of
 // kStride3 iterations the lanes whose voxel has finished take the next
-// voxels of the stream. A lane takes a voxel with its first step done and
-// tested (a plain stream: its first two steps), and takes another at once
-// when that voxel escaped there.
+// voxels of the stream. A lane takes a voxel with its first two steps done
+// and tested, and takes another at once when that voxel escaped there.
 //
 // The dwell: q <- q^2 + c with q = a + b i + e j, c = cr + ci i, the first k
 // with |q_k|^2 > 4, else D; per step a' = (a^2 - (b^2 + e^2)) + cr,
@@ -104,8 +103,8 @@ __device__ __forceinline__ void put_voxel(const Vol3 &v, uint32_t x, uint32_t y,
 // surface telling whether it was one of the first n_surf stream positions.
 // A surface stream (kSurface) takes positions [0, n_surf) first and decides
 // whether their dwells are all equal as it goes: once some voxel has
-// finished with dwell v (1 if one escaped at its first step, else the least
-// of the first stretch in which any finished), another finishing with a
+// finished with dwell v (the least of the first refill or stretch in which
+// any finished), another finishing with a
 // different dwell, or one still running after v iterations, shows the
 // surface is mixed. It then stops (n_all ==
 // n_surf), or (n_all > n_surf: a leaf box) goes on with the surface's other
@@ -149,7 +148,8 @@ __device__ __forceinline__ uint32_t quat_stream(const Vol3 &v, uint32_t n_surf, 
     double a = 0.0, b = 0.0, e = 0.0, a2 = 0.0, s2 = 0.0;
     for (;;) {
         unsigned long long idle = __ballot(!have);
-        bool ones = false;  // this lane finished a voxel at its first step
+        // least and greatest dwell of the voxels this lane finished here
+        uint32_t rlo = 0xffffffffu, rhi = 0u;
         while (idle && next < n) {
             if (!have) {
                 const uint32_t j = next + (uint32_t)__builtin_amdgcn_mbcnt_hi(
@@ -163,41 +163,48 @@ __device__ __forceinline__ uint32_t quat_stream(const Vol3 &v, uint32_t n_surf, 
                     e = axis_point(v.cz, v.hz, z, v.n[2]);
                     a2 = a * a;
                     s2 = b * b + e * e;
-                    // The first step, tested here: most voxels of a volume
-                    // lie outside the set and escape at once, and such a
-                    // lane takes its next voxel in the same refill instead
-                    // of holding a whole stretch.
+                    // The first two steps, tested here: most voxels of a
+                    // volume lie outside the set and escape at once or at
+                    // the next step, and such a lane takes its next voxel
+                    // in the same refill instead of holding a whole stretch.
                     quat_step(a, b, e, a2, s2, cr, ci);
                     k = 1;
-                    if (a2 + s2 > 4.0) {
-                        done(x, y, z, 1u, surf);
-                        have = false;
-                        ones = true;
-                    } else if (!kSurface && D > 1) {
-                        // A plain stream tests the second step here too: of
-                        // the voxels that survive the first, nearly half
-                        // escape at the second.
+                    bool out = a2 + s2 > 4.0;
+                    if (!out && D > 1) {
                         quat_step(a, b, e, a2, s2, cr, ci);
                         k = 2;
-                        if (a2 + s2 > 4.0) {
-                            done(x, y, z, 2u, surf);
-                            have = false;
-                        }
+                        out = a2 + s2 > 4.0;
+                    }
+                    if (out || k >= D) {
+                        done(x, y, z, k, surf);
+                        have = false;
+                        rlo = min(rlo, k);
+                        rhi = max(rhi, k);
                     }
                 }
             }
             next = min(n, next + (uint32_t)__popcll(idle));
             idle = __ballot(!have);
         }
-        // A surface voxel that escaped at the first step has dwell 1, the
-        // least there is: it sets v when none is set yet, and then any
-        // voxel still running (k >= 1) or a v above 1 shows a mixed surface.
-        if (kSurface && scanning && __ballot(ones)) {
+        // A surface voxel finished here has dwell 1 or 2 (D, when D <= 2,
+        // and then every voxel finishes here), below that of any voxel still
+        // running: the least of them sets v when none is set yet, and then a
+        // voxel still running, or one finished here with another dwell,
+        // shows a mixed surface.
+        if (kSurface && scanning && __ballot(rhi != 0)) {
+            uint32_t lo = rlo, hi = rhi;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                lo = min(lo, (uint32_t)__shfl_xor((unsigned int)lo, o));
+                hi = max(hi, (uint32_t)__shfl_xor((unsigned int)hi, o));
+            }
+            lo = __builtin_amdgcn_readfirstlane(lo);
+            hi = __builtin_amdgcn_readfirstlane(hi);
             if (!vset) {
-                val = dec.propose(1u);
+                val = dec.propose(lo);
                 vset = true;
             }
-            if (val != 1 || __ballot(have)) {
+            if (lo != val || hi != val || __ballot(have)) {
                 dec.set_mixed();
                 if (n_all == n_surf)
                     return 1;

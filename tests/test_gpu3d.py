@@ -35,6 +35,13 @@ VOLUMES = [
     (Volume(-1.3, 1.1, -1.2, 1.2, -1.1, 1.3, 131, 97, 75, 256, c=(-0.2, 0.6)), 3, 2, 24),
     (Volume(-1.5, 1.5, -1.5, 1.5, -0.02, 0.02, 100, 90, 2, 300, c=(-1.0, 0.0)), 2, 2, 64),
     (Volume(-2.5, 2.5, -2.5, 2.5, -2.5, 2.5, 60, 60, 60, 100, c=(2.1, 0.3)), 2, 2, 30),
+    # dwell limits at or below the steps tested when a lane takes a voxel:
+    # with D = 1 every dwell is 1 and every box is filled; D = 2 and 3 on
+    # wave boxes and on workgroup boxes
+    (Volume(-1.6, 1.6, -1.6, 1.6, -1.6, 1.6, 30, 27, 25, 1, c=(-0.2, 0.6)), 3, 2, 4),
+    (Volume(-1.6, 1.6, -1.6, 1.6, -1.6, 1.6, 30, 27, 25, 2, c=(-0.2, 0.6)), 3, 2, 4),
+    (Volume(-1.6, 1.6, -1.6, 1.6, -1.6, 1.6, 96, 96, 96, 2, c=(-0.2, 0.6)), 3, 2, 16),
+    (Volume(-1.6, 1.6, -1.6, 1.6, -1.6, 1.6, 96, 96, 96, 3, c=(-0.2, 0.6)), 3, 2, 16),
 ]
 
 
