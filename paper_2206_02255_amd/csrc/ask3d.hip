@@ -235,6 +235,9 @@ __device__ __forceinline__ uint32_t quat_stream(const Vol3 &v, uint32_t n_surf, 
                     k += kStride3;
                 }
             } else {
+                // Kept rolled: unrolled, its sixteen exits hold enough scalar
+                // registers to spill, and the spills lower the occupancy.
+#pragma unroll 1
                 for (uint32_t u = 0; u < kStride3; ++u) {
                     quat_step(a, b, e, a2, s2, cr, ci);
                     if (a2 + s2 > 4.0) {

@@ -331,6 +331,9 @@ __device__ __forceinline__ uint32_t dwell_stream(const Image &im, uint32_t n_rin
                         kbase += kStride;
                     }
                 } else {
+                    // Kept rolled: unrolled, its sixteen exits hold enough
+                    // scalar registers to spill in the common path too.
+#pragma unroll 1
                     for (uint32_t u = 0; u < kStride; ++u) {
                         const double zri = zr * zi;
                         zr = (zr2 - zi2) + cr;
