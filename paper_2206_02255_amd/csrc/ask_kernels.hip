@@ -62,6 +62,8 @@ __device__ __forceinline__ uint32_t dwell_from(double cr, double ci, uint32_t D,
 
 // Iterations between escape tests in the fast loop.
 constexpr uint32_t kStride = 16;
+// Steps tested one by one when a lane takes a Julia-set pixel.
+constexpr uint32_t kRefillSteps = 3;
 
 // The fast loop runs kStride iterations without testing and then tests
 // !(|z|^2 <= 4), which also catches inf and NaN. When |c|^2 <= 3.99, once
@@ -280,6 +282,7 @@ __device__ __forceinline__ uint32_t dwell_stream(const Image &im, uint32_t n_rin
         // pixel is passed over, so this repeats until no lane is idle or the
         // stream is exhausted.
         unsigned long long idle = __ballot(!have);
+        uint32_t rlo = 0xffffffffu, rhi = 0u;  // dwells of the pixels this lane finished here
         while (idle && next < n) {
             if (!have) {
                 const uint32_t j = next + lane_rank(idle);
@@ -291,10 +294,55 @@ __device__ __forceinline__ uint32_t dwell_stream(const Image &im, uint32_t n_rin
                     zr2 = zr * zr;
                     zi2 = zi * zi;
                     kbase = 0;
+                    if (im.julia) {
+                        // A Julia set's pixels start on the orbit, and many
+                        // escape within a few steps: those steps are tested
+                        // here, and such a lane takes its next pixel at once.
+                        bool out = false;
+#pragma unroll 1
+                        for (uint32_t t = 0; t < kRefillSteps && !out && kbase < D; ++t) {
+                            const double zri = zr * zi;
+                            zr = (zr2 - zi2) + cr;
+                            zi = (zri + zri) + ci;
+                            zr2 = zr * zr;
+                            zi2 = zi * zi;
+                            ++kbase;
+                            out = zr2 + zi2 > 4.0;
+                        }
+                        if (out || kbase >= D) {
+                            done(px, py, kbase, ring);
+                            have = false;
+                            rlo = min(rlo, kbase);
+                            rhi = max(rhi, kbase);
+                        }
+                    }
                 }
             }
             next = min(n, next + (uint32_t)__popcll(idle));
             idle = __ballot(!have);
+        }
+        // A ring pixel finished here has a dwell of at most kRefillSteps (or
+        // D, and then every pixel finishes here), below that of any pixel
+        // still running: the least of them sets v when none is set yet, and
+        // then a pixel still running, or one finished here with another
+        // dwell, shows a mixed ring.
+        if (kRing && scanning && __ballot(rhi != 0)) {
+            const uint32_t lo = uniform(wave_min(rlo));
+            const uint32_t hi = uniform(wave_max(rhi));
+            if (!vset) {
+                v = dec.propose(lo);
+                vset = true;
+            }
+            if (lo != v || hi != v || __ballot(have) || dec.mixed()) {
+                dec.set_mixed();
+                if (n_all == n_ring) {
+                    partial = have ? kbase : 0u;
+                    return kMixed;
+                }
+                scanning = false;  // mixed: go on as the leaf
+                n = n_all;
+                continue;
+            }
         }
         if (__ballot(have) == 0)
             break;
