@@ -60,9 +60,8 @@ __device__ __forceinline__ uint32_t dwell_from(double cr, double ci, uint32_t D,
     return D;
 }
 
-// Iterations between escape tests in the fast loop (16 measured 0.5-1 %
-// slower on MI355X, 12 2 % slower).
-constexpr uint32_t kStride = 24;
+// Iterations between escape tests in the fast loop.
+constexpr uint32_t kStride = 16;
 // Steps tested one by one when a lane takes a Julia-set pixel.
 constexpr uint32_t kRefillSteps = 3;
 
@@ -380,7 +379,7 @@ __device__ __forceinline__ uint32_t dwell_stream(const Image &im, uint32_t n_rin
                         kbase += kStride;
                     }
                 } else {
-                    // Kept rolled: unrolled, its kStride exits hold enough
+                    // Kept rolled: unrolled, its sixteen exits hold enough
                     // scalar registers to spill in the common path too.
 #pragma unroll 1
                     for (uint32_t u = 0; u < kStride; ++u) {
