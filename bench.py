@@ -381,7 +381,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the method needs no cross-GPU exchange, and "
-              "this build runs and reports a single MI355X (use --gpus 1)", file=sys.stderr)
+              "the benchmark runs and reports a single MI355X (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch
